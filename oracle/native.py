@@ -1,0 +1,137 @@
+"""ctypes front end of the C oracle (``oracle/perm_oracle.c``) -- test infrastructure.
+
+Only tests/, ``__graft_entry__.smoke()`` and bench.py's CPU-baseline leg may
+use this module.  :func:`build` compiles the C file with gcc into
+``oracle/_build/libpermoracle.so``; the functions here load it on first use
+(building it if it is missing).
+
+The C code evaluates the Store-zechin stored sub-permanents (section 4 of the
+paper) on dense bitmask-indexed tables; see the header of perm_oracle.c for
+the per-entry arithmetic (fp64 FMA chain for complex, exact 128-bit
+accumulation then ``%`` for residues).
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+import subprocess
+import threading
+from typing import List, Optional, Sequence
+
+import numpy as np
+
+from . import exact
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+_SRC = os.path.join(_HERE, "perm_oracle.c")
+_BUILD_DIR = os.path.join(_HERE, "_build")
+_LIB_PATH = os.path.join(_BUILD_DIR, "libpermoracle.so")
+_lock = threading.Lock()
+_lib: Optional[ctypes.CDLL] = None
+
+MODE_MEMO = 0
+MODE_LAYERS = 1
+
+
+def build(force: bool = True) -> str:
+    """Compile the C oracle (gcc, OpenMP, no FP contraction)."""
+    os.makedirs(_BUILD_DIR, exist_ok=True)
+    if force or not os.path.exists(_LIB_PATH):
+        tmp = _LIB_PATH + f".tmp{os.getpid()}"
+        cmd = ["gcc", "-O2", "-ffp-contract=off", "-fno-fast-math", "-fopenmp",
+               "-shared", "-fPIC", "-o", tmp, _SRC, "-lm"]
+        subprocess.run(cmd, check=True)
+        os.replace(tmp, _LIB_PATH)
+    return _LIB_PATH
+
+
+def _load() -> ctypes.CDLL:
+    global _lib
+    with _lock:
+        if _lib is None:
+            if not os.path.exists(_LIB_PATH):
+                build(force=False)
+            lib = ctypes.CDLL(_LIB_PATH)
+            dp = ctypes.POINTER(ctypes.c_double)
+            up = ctypes.POINTER(ctypes.c_uint64)
+            lib.oracle_per_c128.argtypes = [ctypes.c_int, dp, ctypes.c_int, ctypes.c_int, dp]
+            lib.oracle_per_c128.restype = ctypes.c_int
+            lib.oracle_per_abs.argtypes = [ctypes.c_int, dp, ctypes.c_int, dp]
+            lib.oracle_per_abs.restype = ctypes.c_int
+            lib.oracle_per_modp.argtypes = [ctypes.c_int, up, ctypes.c_uint64, ctypes.c_int,
+                                            ctypes.c_int, up]
+            lib.oracle_per_modp.restype = ctypes.c_int
+            lib.oracle_max_threads.argtypes = []
+            lib.oracle_max_threads.restype = ctypes.c_int
+            _lib = lib
+    return _lib
+
+
+def _check(rc: int, what: str):
+    if rc == -2:
+        raise MemoryError(f"{what}: out of host memory")
+    if rc != 0:
+        raise ValueError(f"{what}: bad arguments (rc={rc})")
+
+
+def _as_c128(A) -> np.ndarray:
+    A = np.ascontiguousarray(np.asarray(A, dtype=np.complex128))
+    if A.ndim != 2 or A.shape[0] != A.shape[1]:
+        raise ValueError("square matrix expected")
+    return A
+
+
+def per_c128(A, mode: int = MODE_LAYERS, nthreads: int = 0) -> complex:
+    """fp64 Store-zechin permanent of a complex matrix (canonical FMA chain)."""
+    A = _as_c128(A)
+    n = A.shape[0]
+    out = np.zeros(2, dtype=np.float64)
+    flat = A.view(np.float64)
+    rc = _load().oracle_per_c128(n, flat.ctypes.data_as(ctypes.POINTER(ctypes.c_double)),
+                                 mode, nthreads, out.ctypes.data_as(ctypes.POINTER(ctypes.c_double)))
+    _check(rc, "oracle_per_c128")
+    return complex(out[0], out[1])
+
+
+def per_c128_bits(A, mode: int = MODE_LAYERS, nthreads: int = 0) -> np.ndarray:
+    """Same as :func:`per_c128` but returns the two doubles as uint64 bit patterns."""
+    z = per_c128(A, mode, nthreads)
+    return np.array([z.real, z.imag], dtype=np.float64).view(np.uint64)
+
+
+def per_abs(A, nthreads: int = 0) -> float:
+    """fp64 per(|A|), the scale of the complex tolerance |d| <= tol * per(|A|)."""
+    A = _as_c128(A)
+    n = A.shape[0]
+    out = np.zeros(1, dtype=np.float64)
+    flat = A.view(np.float64)
+    rc = _load().oracle_per_abs(n, flat.ctypes.data_as(ctypes.POINTER(ctypes.c_double)),
+                                nthreads, out.ctypes.data_as(ctypes.POINTER(ctypes.c_double)))
+    _check(rc, "oracle_per_abs")
+    return float(out[0])
+
+
+def per_modp(R, p: int, mode: int = MODE_LAYERS, nthreads: int = 0) -> int:
+    """Store-zechin permanent mod p of a matrix of residues in [0, p), p < 2^61."""
+    R = np.ascontiguousarray(np.asarray(R, dtype=np.uint64))
+    if R.ndim != 2 or R.shape[0] != R.shape[1]:
+        raise ValueError("square matrix expected")
+    n = R.shape[0]
+    out = np.zeros(1, dtype=np.uint64)
+    up = ctypes.POINTER(ctypes.c_uint64)
+    rc = _load().oracle_per_modp(n, R.ctypes.data_as(up), ctypes.c_uint64(p), mode, nthreads,
+                                 out.ctypes.data_as(up))
+    _check(rc, "oracle_per_modp")
+    return int(out[0])
+
+
+def per_int(A, mode: int = MODE_LAYERS, nthreads: int = 0, redundant: int = 1) -> int:
+    """Exact integer permanent: C residues per prime, Garner in Python."""
+    def per_mod(res: List[List[int]], p: int) -> int:
+        return per_modp(np.array(res, dtype=np.uint64).reshape(len(res), len(res)), p,
+                        mode=mode, nthreads=nthreads)
+    return exact.per_int_multimodular(A, per_mod, redundant=redundant)
+
+
+def max_threads() -> int:
+    return int(_load().oracle_max_threads())

@@ -1,0 +1,310 @@
+/*
+ * CPU oracle for the permanent -- TEST INFRASTRUCTURE ONLY.
+ *
+ * Only tests/, __graft_entry__.smoke() and bench.py's CPU-baseline leg may
+ * load this library.  It shares no code, header, table or constant with the
+ * HIP library under paper_1802_02779_amd/: it is written from the paper.
+ *
+ * What it computes (Su & Zheng, section 4 "Store-zechin"): the permanent of
+ * an n x n matrix developed along the last row, recursively, with every
+ * sub-permanent stored once and reused.  A stored sub-permanent is
+ *
+ *     F(S) = per(rows 0..|S|-1 of A, columns S),   S a subset of {0..n-1},
+ *
+ * i.e. the paper's A_{u;v} with u = the last n-|S| rows and v = the
+ * complement of S (notation of section 4).  Development of the last of its
+ * rows (property 4 of section 3.1) gives
+ *
+ *     F(S) = sum over j in S, ascending, of a[|S|-1][j] * F(S \ {j}),
+ *     F({j}) = a[0][j],  F(empty) = 1.
+ *
+ * The tables are indexed by the bitmask of S (2^n entries).  Two evaluation
+ * orders of the same stored values are offered:
+ *   memo   -- the paper's order: recurse from F({0..n-1}) along the last
+ *             row, evaluate each F(S) the first time it is needed, store it;
+ *             single-threaded;
+ *   layers -- every F(S) with |S| = k before any with |S| = k+1 (k = 2..n);
+ *             OpenMP over the masks of one popcount.
+ * Each F(S) has exactly one arithmetic definition (below), so both orders
+ * produce bitwise-identical tables.
+ *
+ * Arithmetic of one stored value:
+ *   complex128: acc = 0 + 0i; for j ascending in S, with a = a[k-1][j] and
+ *     p = F(S\{j}):  acc.re = fma( a.re, p.re, acc.re);
+ *                    acc.re = fma(-a.im, p.im, acc.re);
+ *                    acc.im = fma( a.re, p.im, acc.im);
+ *                    acc.im = fma( a.im, p.re, acc.im);
+ *     (round to nearest even, no reassociation; the paper works in exact
+ *     arithmetic and fixes no order, so this one is chosen and documented).
+ *   mod p (p < 2^61): acc = sum of a*p as an exact unsigned 128-bit integer
+ *     (at most 30 terms below 2^122 each, so no overflow), then acc % p.
+ *   |A| (per of entrywise moduli, for the complex tolerance): the complex
+ *     chain's real part with a = |a_ij| (hypot) and non-negative values.
+ *
+ * Build: gcc -O2 -ffp-contract=off -fno-fast-math -fopenmp -shared -fPIC.
+ * Returns 0 on success, -1 on bad arguments, -2 when memory runs out.
+ */
+#include <math.h>
+#include <stdint.h>
+#include <stdlib.h>
+#include <string.h>
+#ifdef _OPENMP
+#include <omp.h>
+#endif
+
+#define ORACLE_N_MAX 30
+
+typedef unsigned __int128 u128;
+
+static int popcount32(uint32_t x) { return __builtin_popcount(x); }
+
+/* ---------------------------------------------------------------- complex */
+
+typedef struct {
+    int n;
+    const double *a; /* row-major, interleaved (re, im), n*n entries */
+    double *tab;     /* 2^n entries of (re, im) */
+    uint8_t *done;   /* 2^n bits */
+} c128_state;
+
+static void c128_value(const double *a, int n, const double *tab, uint32_t S,
+                       double *out_re, double *out_im)
+{
+    int k = popcount32(S);
+    const double *row = a + 2 * (size_t)(k - 1) * (size_t)n;
+    double re = 0.0, im = 0.0;
+    for (int j = 0; j < n; j++) {
+        if (!((S >> j) & 1u))
+            continue;
+        uint32_t P = S & ~(1u << j);
+        double ar = row[2 * j], ai = row[2 * j + 1];
+        double pr = tab[2 * (size_t)P], pi = tab[2 * (size_t)P + 1];
+        re = fma(ar, pr, re);
+        re = fma(-ai, pi, re);
+        im = fma(ar, pi, im);
+        im = fma(ai, pr, im);
+    }
+    *out_re = re;
+    *out_im = im;
+}
+
+static void c128_memo_visit(c128_state *st, uint32_t S)
+{
+    /* The paper's order: develop along the last row; evaluate each needed
+     * minor (recursively) the first time, then reuse the stored value. */
+    if (st->done[S >> 3] & (1u << (S & 7)))
+        return;
+    for (int j = 0; j < st->n; j++) {
+        if ((S >> j) & 1u) {
+            uint32_t P = S & ~(1u << j);
+            c128_memo_visit(st, P);
+        }
+    }
+    c128_value(st->a, st->n, st->tab, S, &st->tab[2 * (size_t)S], &st->tab[2 * (size_t)S + 1]);
+    st->done[S >> 3] |= (uint8_t)(1u << (S & 7));
+}
+
+static int c128_setup(int n, const double *a, double **tab, uint8_t **done)
+{
+    size_t N = (size_t)1 << n;
+    *tab = (double *)malloc(2 * N * sizeof(double));
+    *done = (uint8_t *)calloc((N + 7) / 8, 1);
+    if (!*tab || !*done) {
+        free(*tab);
+        free(*done);
+        return -2;
+    }
+    for (int j = 0; j < n; j++) {
+        uint32_t S = 1u << j;
+        (*tab)[2 * (size_t)S] = a[2 * j];
+        (*tab)[2 * (size_t)S + 1] = a[2 * j + 1];
+        (*done)[S >> 3] |= (uint8_t)(1u << (S & 7));
+    }
+    return 0;
+}
+
+/* mode: 0 = memo (paper's order, one thread), 1 = layers (OpenMP) */
+int oracle_per_c128(int n, const double *a, int mode, int nthreads, double *out)
+{
+    if (n < 0 || n > ORACLE_N_MAX || !out || (n > 0 && !a))
+        return -1;
+    if (n == 0) {
+        out[0] = 1.0;
+        out[1] = 0.0;
+        return 0;
+    }
+    if (n == 1) {
+        out[0] = a[0];
+        out[1] = a[1];
+        return 0;
+    }
+    double *tab;
+    uint8_t *done;
+    int rc = c128_setup(n, a, &tab, &done);
+    if (rc)
+        return rc;
+    uint32_t full = (uint32_t)(((uint64_t)1 << n) - 1);
+    if (mode == 0) {
+        c128_state st = {n, a, tab, done};
+        c128_memo_visit(&st, full);
+    } else {
+        int64_t N = (int64_t)1 << n;
+#ifdef _OPENMP
+        if (nthreads > 0)
+            omp_set_num_threads(nthreads);
+#endif
+        for (int k = 2; k <= n; k++) {
+#pragma omp parallel for schedule(static, 4096)
+            for (int64_t S = 0; S < N; S++) {
+                if (popcount32((uint32_t)S) != k)
+                    continue;
+                c128_value(a, n, tab, (uint32_t)S, &tab[2 * S], &tab[2 * S + 1]);
+            }
+        }
+    }
+    out[0] = tab[2 * (size_t)full];
+    out[1] = tab[2 * (size_t)full + 1];
+    free(tab);
+    free(done);
+    return 0;
+}
+
+/* ------------------------------------------------------------------ |A| */
+
+int oracle_per_abs(int n, const double *a, int nthreads, double *out)
+{
+    if (n < 0 || n > ORACLE_N_MAX || !out || (n > 0 && !a))
+        return -1;
+    if (n == 0) {
+        *out = 1.0;
+        return 0;
+    }
+    size_t N = (size_t)1 << n;
+    double *mod = (double *)malloc((size_t)n * n * sizeof(double));
+    double *tab = (double *)malloc(N * sizeof(double));
+    if (!mod || !tab) {
+        free(mod);
+        free(tab);
+        return -2;
+    }
+    for (size_t i = 0; i < (size_t)n * n; i++)
+        mod[i] = hypot(a[2 * i], a[2 * i + 1]);
+    for (int j = 0; j < n; j++)
+        tab[(size_t)1 << j] = mod[j];
+#ifdef _OPENMP
+    if (nthreads > 0)
+        omp_set_num_threads(nthreads);
+#endif
+    for (int k = 2; k <= n; k++) {
+        const double *row = mod + (size_t)(k - 1) * n;
+#pragma omp parallel for schedule(static, 4096)
+        for (int64_t S = 0; S < (int64_t)N; S++) {
+            if (popcount32((uint32_t)S) != k)
+                continue;
+            double acc = 0.0;
+            for (int j = 0; j < n; j++)
+                if ((S >> j) & 1)
+                    acc = fma(row[j], tab[S & ~((int64_t)1 << j)], acc);
+            tab[S] = acc;
+        }
+    }
+    *out = tab[N - 1];
+    free(mod);
+    free(tab);
+    return 0;
+}
+
+/* ----------------------------------------------------------------- mod p */
+
+typedef struct {
+    int n;
+    const uint64_t *a; /* residues in [0, p), row-major */
+    uint64_t p;
+    uint64_t *tab;
+    uint8_t *done;
+} modp_state;
+
+static uint64_t modp_value(const uint64_t *a, int n, uint64_t p, const uint64_t *tab, uint32_t S)
+{
+    int k = popcount32(S);
+    const uint64_t *row = a + (size_t)(k - 1) * n;
+    u128 acc = 0;
+    for (int j = 0; j < n; j++)
+        if ((S >> j) & 1u)
+            acc += (u128)row[j] * tab[S & ~(1u << j)];
+    return (uint64_t)(acc % p);
+}
+
+static void modp_memo_visit(modp_state *st, uint32_t S)
+{
+    if (st->done[S >> 3] & (1u << (S & 7)))
+        return;
+    for (int j = 0; j < st->n; j++)
+        if ((S >> j) & 1u)
+            modp_memo_visit(st, S & ~(1u << j));
+    st->tab[S] = modp_value(st->a, st->n, st->p, st->tab, S);
+    st->done[S >> 3] |= (uint8_t)(1u << (S & 7));
+}
+
+/* a: residues in [0, p); p must be below 2^61 so 30 products fit 128 bits. */
+int oracle_per_modp(int n, const uint64_t *a, uint64_t p, int mode, int nthreads, uint64_t *out)
+{
+    if (n < 0 || n > ORACLE_N_MAX || !out || (n > 0 && !a) || p < 2 || p >= ((uint64_t)1 << 61))
+        return -1;
+    for (size_t i = 0; i < (size_t)n * n; i++)
+        if (a[i] >= p)
+            return -1;
+    if (n == 0) {
+        *out = 1 % p;
+        return 0;
+    }
+    if (n == 1) {
+        *out = a[0];
+        return 0;
+    }
+    size_t N = (size_t)1 << n;
+    uint64_t *tab = (uint64_t *)malloc(N * sizeof(uint64_t));
+    uint8_t *done = (uint8_t *)calloc((N + 7) / 8, 1);
+    if (!tab || !done) {
+        free(tab);
+        free(done);
+        return -2;
+    }
+    for (int j = 0; j < n; j++) {
+        uint32_t S = 1u << j;
+        tab[S] = a[j];
+        done[S >> 3] |= (uint8_t)(1u << (S & 7));
+    }
+    uint32_t full = (uint32_t)(N - 1);
+    if (mode == 0) {
+        modp_state st = {n, a, p, tab, done};
+        modp_memo_visit(&st, full);
+    } else {
+#ifdef _OPENMP
+        if (nthreads > 0)
+            omp_set_num_threads(nthreads);
+#endif
+        for (int k = 2; k <= n; k++) {
+#pragma omp parallel for schedule(static, 4096)
+            for (int64_t S = 0; S < (int64_t)N; S++) {
+                if (popcount32((uint32_t)S) != k)
+                    continue;
+                tab[S] = modp_value(a, n, p, tab, (uint32_t)S);
+            }
+        }
+    }
+    *out = tab[full];
+    free(tab);
+    free(done);
+    return 0;
+}
+
+/* Number of OpenMP threads a parallel region would use (for reporting). */
+int oracle_max_threads(void)
+{
+#ifdef _OPENMP
+    return omp_get_max_threads();
+#else
+    return 1;
+#endif
+}
