@@ -1,0 +1,238 @@
+/*
+ * perm.h -- C ABI of libpermgpu: Store-zechin permanents on MI355X (gfx950).
+ *
+ * The problem (Su & Zheng, section 3.1, eq. (1)): the permanent
+ *     per(A) = sum over permutations s of {1..n} of prod_i a[i, s(i)]
+ * of an n x n matrix A = (a_ij).
+ *
+ * The method (section 4, "Store-zechin"): develop per(A) along its last row
+ * (property 4 of section 3.1), recursively, storing every sub-permanent the
+ * first time it is evaluated and reusing it afterwards (sections 4.2-4.3:
+ * each repeated minor is computed once).  A stored sub-permanent is
+ *     F(S) = per(rows 1..|S| of A, columns S),  S a subset of the columns,
+ * so that F(S) = sum over j in S (ascending) of a[|S|, j] * F(S \ {j}) and
+ * per(A) = F({1..n}).  The library evaluates all F(S) with |S| = k before
+ * those with |S| = k+1 ("layers" k = 1..n) on the GPU.
+ *
+ * Numbers:
+ *   PERM_COMPLEX128 -- fp64 complex; each F(S) is one fixed chain of fused
+ *     multiply-adds over j ascending (re += a.re*p.re; re += -a.im*p.im;
+ *     im += a.re*p.im; im += a.im*p.re), so results do not depend on the
+ *     launch configuration and are bitwise reproducible.
+ *   PERM_INT64 -- exact: per(A) mod several primes p < 2^61 (largest first),
+ *     chosen so their product exceeds twice a bound on |per(A)|, plus one
+ *     redundant prime that must agree; recombined by Chinese remaindering on
+ *     the host into a signed multi-limb integer (perm_int_t).
+ *
+ * Conventions shared by every call:
+ *   - Return value: PERM_OK (0), PERM_PENDING (1, server only) or a negative
+ *     error code; perm_last_error() then holds a message (thread-local).
+ *     No C++ exception ever crosses this boundary.
+ *   - Matrices are row-major: entry (i, j) at a[i * lda + j], 0-based,
+ *     lda >= n.  int64 entries are int64_t; complex entries perm_c128_t.
+ *   - "stream" is a hipStream_t passed as void* (NULL = the null stream).
+ *   - The caller owns every buffer it passes, including the device
+ *     workspace; the library never frees caller memory.
+ *   - NaN/Inf inputs are outside the contract (they propagate by IEEE rules).
+ */
+#ifndef PERM_H
+#define PERM_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define PERM_N_MAX 30        /* largest order accepted by perm_solve */
+#define PERM_BATCH_N_MAX 12  /* largest order accepted by perm_solve_batch */
+#define PERM_INT_LIMBS 32    /* 2048-bit magnitude: enough for any int64 input at n = 30 */
+#define PERM_MAX_PRIMES 40   /* primes the integer path may use */
+
+typedef enum { PERM_INT64 = 0, PERM_COMPLEX128 = 1 } perm_dtype_t;
+
+typedef struct {
+    double re, im;
+} perm_c128_t;
+
+/* value = sign * sum_{i < nlimbs} limb[i] * 2^(64 i); sign is -1, 0 or +1. */
+typedef struct {
+    int32_t sign;
+    uint32_t nlimbs;
+    uint64_t limb[PERM_INT_LIMBS];
+} perm_int_t;
+
+enum {
+    PERM_OK = 0,
+    PERM_PENDING = 1,      /* server: ticket not finished yet */
+    PERM_EINVAL = -1,      /* null pointer, bad dtype, n < 0, lda < n, bad flags */
+    PERM_ERANGE = -2,      /* n above the limit of the call */
+    PERM_ENOMEM = -3,      /* workspace too small / footprint above the budget */
+    PERM_EDEVICE = -4,     /* a HIP call failed, or the redundant prime disagreed */
+    PERM_EAGAIN = -5,      /* server queue full (back-pressure) */
+    PERM_ENOTFOUND = -6,   /* unknown or already consumed ticket */
+    PERM_ECANCELLED = -7   /* server destroyed before the request finished */
+};
+
+/* ------------------------------------------------------------ library --- */
+
+/* Message of the last non-OK return on the calling thread ("" if none). */
+const char *perm_last_error(void);
+
+/* ABI version (major * 10000 + minor * 100 + patch). */
+int perm_version(void);
+
+/* The i-th prime of the integer path (i = 0 is 2^61 - 1, then descending).
+ * Returns PERM_EINVAL if i is outside [0, PERM_MAX_PRIMES) or p is NULL. */
+int perm_prime(int i, uint64_t *p);
+
+/* ------------------------------------------------- single-matrix solve --- */
+
+/* Device workspace bytes perm_solve / perm_solve_async need for order n
+ * (two layer tables of the largest layer, C(n, n/2) entries, plus the matrix
+ * and the scalars).  For PERM_INT64 the size lets three primes share one
+ * sweep; a smaller workspace still works (fewer primes per sweep, more
+ * sweeps) as long as it holds one prime's tables.  Returns 0 for a bad
+ * dtype or n outside [0, PERM_N_MAX]. */
+size_t perm_workspace_bytes(perm_dtype_t dt, int n);
+
+/* per(A) of one n x n matrix, 0 <= n <= PERM_N_MAX.
+ *   a         host matrix (int64_t or perm_c128_t), row-major with lda.
+ *   result    host output: perm_int_t* (PERM_INT64) or perm_c128_t*.
+ *   workspace device memory of at least perm_workspace_bytes(dt, n) bytes
+ *             (ws_bytes says how much there is); contents are scratch.
+ *   stream    the stream every copy and kernel is ordered on.
+ * Host-synchronous: returns after the result is in *result.  Re-entrant when
+ * calls use distinct workspaces.  n = 0 gives 1 (empty product); n = 1 gives
+ * a[0].  Errors: PERM_EINVAL, PERM_ERANGE (n > PERM_N_MAX), PERM_ENOMEM
+ * (ws_bytes too small), PERM_EDEVICE. */
+int perm_solve(perm_dtype_t dt, int n, const void *a, int64_t lda, void *result,
+               void *workspace, size_t ws_bytes, void *stream);
+
+/* Stream-ordered complex128 solve with device input and output: reads the
+ * device matrix a_dev (row-major, lda), writes per(A) to *result_dev (device),
+ * and returns as soon as the work is queued on `stream`.  Same workspace
+ * rules and result bits as perm_solve(PERM_COMPLEX128, ...).  The caller
+ * must keep a_dev, result_dev and the workspace alive until the stream has
+ * passed the work. */
+int perm_solve_async(int n, const perm_c128_t *a_dev, int64_t lda, perm_c128_t *result_dev,
+                     void *workspace, size_t ws_bytes, void *stream);
+
+/* ------------------------------------------------------------- batch --- */
+
+#define PERM_BATCH_SYNC 1u   /* wait for completion before returning */
+#define PERM_BATCH_GRAPH 2u  /* launch through a captured HIP graph (replayed on repeat calls) */
+#define PERM_BATCH_REUSE 4u  /* ns/offsets are the same as in the previous call with this
+                              * workspace: skip rebuilding and re-uploading the work list */
+
+/* Device workspace bytes for a batch (host array ns of `count` orders). */
+size_t perm_batch_workspace_bytes(perm_dtype_t dt, int count, const int32_t *ns);
+
+/* Many independent permanents of orders 0..PERM_BATCH_N_MAX in one
+ * persistent launch: the matrices are dealt to workgroups from a work list
+ * sorted by cost (largest first); each workgroup keeps a matrix's whole table
+ * of stored sub-permanents on chip.
+ *   ns[count]      host, orders.
+ *   offsets[count] host, element offset of matrix i inside mats.
+ *   mats           PERM_COMPLEX128: device perm_c128_t array;
+ *                  PERM_INT64: HOST int64_t array (bounds and primes are
+ *                  chosen on the host).  Matrices are row-major, lda = n.
+ *   results        PERM_COMPLEX128: device perm_c128_t[count];
+ *                  PERM_INT64: host perm_int_t[count] (the call is then
+ *                  always synchronous).
+ *   flags          PERM_BATCH_* bits.
+ * Complex results are bitwise equal to perm_solve on the same matrix.
+ * Stream-ordered unless PERM_BATCH_SYNC is given.  With PERM_BATCH_GRAPH the
+ * launch is captured once per (workspace, mats, results, count) and replayed;
+ * PERM_BATCH_REUSE then skips the host work entirely. */
+int perm_solve_batch(perm_dtype_t dt, int count, const int32_t *ns, const int64_t *offsets,
+                     const void *mats, void *results, void *workspace, size_t ws_bytes,
+                     void *stream, uint32_t flags);
+
+/* ------------------------------------------------------------ server --- */
+
+typedef struct perm_server perm_server_t;
+
+typedef struct {
+    void *pool;             /* device arena the server carves tables from (caller-owned) */
+    size_t pool_bytes;      /* its size */
+    size_t budget_bytes;    /* admission budget: sum of 16 * 2^n over admitted requests;
+                               0 means pool_bytes */
+    int max_large_slots;    /* concurrent large solves (each on its own stream); >= 1 */
+    int queue_capacity;     /* pending requests before submit returns PERM_EAGAIN; >= 1 */
+    int small_n_max;        /* orders <= this go through the batched kernel (<= 12) */
+    int max_small_batch;    /* most small requests in one batched launch; >= 1 */
+} perm_server_config_t;
+
+typedef struct {
+    double t_submit, t_admit, t_start, t_done; /* seconds on a monotonic clock */
+    int n;
+    int status;                                /* PERM_OK or the request's error */
+} perm_req_stats_t;
+
+/* Start a server (complex128 requests) with its own scheduler thread and
+ * streams.  The pool must stay allocated until perm_server_destroy returns. */
+int perm_server_create(const perm_server_config_t *cfg, perm_server_t **out);
+
+/* Queue per(A) of a host complex128 matrix (copied before return; the caller
+ * may reuse `a` at once).  Returns PERM_EAGAIN when the queue is full,
+ * PERM_ENOMEM when 16 * 2^n exceeds the whole budget, PERM_ERANGE for
+ * n > PERM_N_MAX.  *ticket identifies the request. */
+int perm_server_submit(perm_server_t *s, perm_dtype_t dt, int n, const void *a, int64_t lda,
+                       uint64_t *ticket);
+
+/* PERM_PENDING while the request runs; once finished, writes the
+ * perm_c128_t result and (if stats != NULL) its timings, releases the ticket
+ * and returns the request's status.  PERM_ENOTFOUND for unknown or consumed
+ * tickets. */
+int perm_server_poll(perm_server_t *s, uint64_t ticket, void *result, perm_req_stats_t *stats);
+
+/* Stop the scheduler, wait for work on the device, fail still-queued
+ * requests with PERM_ECANCELLED, free the server.  Unpolled results are
+ * dropped. */
+int perm_server_destroy(perm_server_t *s);
+
+/* ------------------------------------------------------ tuning / stats --- */
+
+/* Tile and schedule parameters.  layer_t: columns per low window of the
+ * layer sweep for order n (the others form the tile's fixed high part);
+ * batch_group: threads that share one matrix in the batched kernel. */
+typedef struct {
+    int layer_t[PERM_N_MAX + 1];          /* 0 = library default */
+    int layer_xcd_remap[PERM_N_MAX + 1];  /* -1 = default, 0/1 = off/on */
+    int batch_group[PERM_BATCH_N_MAX + 1];/* 0 = library default */
+} perm_tuning_t;
+
+/* Read / replace the process-wide tuning table (values are validated;
+ * PERM_EINVAL on an impossible entry).  perm_tuning_load/_save use a small
+ * JSON file keyed by GPU architecture, CU count and HIP runtime version; a
+ * file for another key is ignored (returns PERM_ENOTFOUND). */
+int perm_tuning_get(perm_tuning_t *out);
+int perm_tuning_set(const perm_tuning_t *in);
+int perm_tuning_load(const char *path);
+int perm_tuning_save(const char *path);
+/* The key string the tuning file must carry for the current device. */
+int perm_tuning_key(char *buf, size_t len);
+
+/* Per-kernel timing with HIP events on the launch stream.  While enabled,
+ * every layer-sweep launch is bracketed by events; perm_profile_read
+ * synchronizes on them and returns the summed duration (ms) and the number
+ * of launches per kernel family since the last read. */
+typedef struct {
+    double layer_c128_ms;
+    int64_t layer_c128_launches;
+    double layer_modp_ms;
+    int64_t layer_modp_launches;
+    double batch_ms;
+    int64_t batch_launches;
+} perm_profile_t;
+
+int perm_profile_enable(int on);
+int perm_profile_read(perm_profile_t *out);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* PERM_H */

@@ -1,0 +1,5 @@
+// The library's single device translation unit: the batched kernel shares
+// the rank tables (binomials, popcount-ordered masks) built for the layer
+// sweep, so both are compiled together.
+#include "perm_layers.hip"
+#include "perm_batch.hip"

@@ -1,0 +1,43 @@
+// Host-side internals of libpermgpu shared by perm_host.cpp and perm_server.cpp.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstdarg>
+#include <cstdint>
+#include <string>
+#include <vector>
+
+#include "../../include/perm.h"
+#include "perm_internal.h"
+
+namespace permgpu {
+
+// Records the message for perm_last_error() and returns `code`.
+int set_error(int code, const char *fmt, ...);
+int hip_error(hipError_t e, const char *what);
+
+// Current device index, with tables built (once per device).
+int prepare_device(hipStream_t s, int *device);
+
+// Tuning lookups (process-wide table, defaults when unset).
+int tuned_layer_t(int n);
+int tuned_layer_remap(int n);
+int tuned_batch_group(int n, size_t lds_bytes, int elem_bytes);
+
+// Complex solve of a device matrix into a device result, stream-ordered.
+int solve_c128_device(int n, const void *a_dev, int64_t lda, void *result_dev, void *ws,
+                      size_t ws_bytes, hipStream_t s);
+
+// Workspace bytes of the complex path (both solve entry points).
+size_t c128_workspace_bytes(int n);
+
+// Profiling hooks.
+bool profiling_on();
+void profile_record(int kind, hipEvent_t start, hipEvent_t stop);  // kind 0 c128, 1 modp, 2 batch
+hipEvent_t profile_event();
+
+// Monotonic clock in seconds.
+double now_seconds();
+
+}  // namespace permgpu

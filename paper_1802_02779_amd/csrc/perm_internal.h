@@ -1,0 +1,133 @@
+// Internal declarations of libpermgpu shared by its HIP and host sources.
+//
+// Stored sub-permanents (section 4 of the paper): F(S) = per(rows 1..|S|,
+// columns S).  Layer k holds F(S) for every k-subset S of the n columns,
+// ranked in colexicographic order:
+//     rank(S) = sum_{i=1..k} C(s_i, i),   s_1 < ... < s_k   (0-based columns),
+// which is also increasing bitmask order.  The layer sweep computes layer k
+// from layer k-1 tile by tile.  A tile fixes the "high" part T = S & [t, n)
+// (|T| = m) and runs over every "low" part L = S & [0, t) with |L| = k' = k-m:
+//   * the tile's outputs have contiguous ranks  base(T, k') + rank_t(L),
+//     rank_t(L) in [0, C(t, k'));
+//   * removing a low column l in L leads to layer k-1 entries with the same T
+//     and |L| = k'-1: one contiguous window of C(t, k'-1) entries, staged in
+//     LDS and gathered through a precomputed table ("lowtab");
+//   * removing a high column h in T leads to a window of C(t, k') entries
+//     aligned 1:1 with the tile's outputs (same rank_t(L)): read straight from
+//     HBM, coalesced.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stddef.h>
+#include <stdint.h>
+
+namespace permgpu {
+
+constexpr int kNMax = 30;
+constexpr int kTMax = 15;        // largest low window (columns) of a tile
+constexpr int kHighBits = 17;    // largest high part (columns) of a tile
+constexpr int kBatchNMax = 12;   // largest order of the on-chip batched kernel
+constexpr int kRPMax = 3;        // primes that share one integer sweep
+constexpr int kMaxGroups = 32;   // k' groups in one layer launch
+
+struct BinomTable {
+    uint32_t v[33][33];
+};
+
+constexpr BinomTable make_binom() {
+    BinomTable b{};
+    for (int i = 0; i <= 32; i++) {
+        b.v[i][0] = 1;
+        for (int j = 1; j <= i; j++)
+            b.v[i][j] = b.v[i - 1][j - 1] + (j <= i - 1 ? b.v[i - 1][j] : 0u);
+    }
+    return b;
+}
+
+inline constexpr BinomTable kBinom = make_binom();
+
+constexpr uint32_t binom_host(int i, int j) {
+    return (i < 0 || j < 0 || i > 32 || j > 32) ? 0u : kBinom.v[i][j];
+}
+
+// lowtab layout: for each t in 1..kTMax, for each k' in 1..t, entries
+// [p * C(t,k') + rank_t(L)] for p in [0, k'): (rank_{t}(L \ {l_p}) | l_p << 16)
+// where l_p is the p-th smallest column of L.
+constexpr uint32_t lowtab_t_base(int t) {  // sum_{s < t} s * 2^(s-1)
+    uint32_t s = 0;
+    for (int u = 1; u < t; u++) s += (uint32_t)u << (u - 1);
+    return s;
+}
+constexpr uint32_t lowtab_kp_off(int t, int kp) {  // sum_{k'' < k'} k'' * C(t, k'')
+    uint32_t s = 0;
+    for (int u = 1; u < kp; u++) s += (uint32_t)u * binom_host(t, u);
+    return s;
+}
+constexpr uint32_t kLowtabEntries = lowtab_t_base(kTMax + 1);
+
+// highlist: every mask below 2^kHighBits, sorted by (popcount, value).
+// Masks of popcount m below 2^nh are the first C(nh, m) entries of block m.
+constexpr uint32_t highlist_off(int m) {
+    uint32_t s = 0;
+    for (int u = 0; u < m; u++) s += binom_host(kHighBits, u);
+    return s;
+}
+
+struct LayerArgs {
+    int n, k, t;
+    int ngroups;
+    int remap;                // XCD-aware tile order
+    uint32_t lds_window;      // entries reserved for the largest low window
+    int32_t kp[kMaxGroups];   // k' of group g
+    uint32_t start[kMaxGroups + 1];  // first tile of group g (prefix sums)
+    uint32_t ck[kMaxGroups];         // C(t, k'): outputs per tile
+    uint32_t low_off[kMaxGroups];    // lowtab offset of (t, k')
+    uint32_t high_off[kMaxGroups];   // highlist offset of popcount m = k - k'
+};
+
+// Fills LayerArgs for layer k of order n with low window t; returns the
+// number of tiles (grid size).
+uint32_t plan_layer(int n, int k, int t, int remap, LayerArgs *a);
+
+// Dynamic LDS bytes of a layer launch.
+size_t layer_lds_bytes_c128(const LayerArgs &a);
+size_t layer_lds_bytes_modp(const LayerArgs &a, int rp);
+
+// ---- launchers (perm_layers.hip); all return hipError_t of the launch ----
+hipError_t ensure_tables(int device, hipStream_t s);
+hipError_t launch_pack_c128(const void *a_dev, int64_t lda, int n, void *packed, void *layer1,
+                            hipStream_t s);
+hipError_t launch_layer_c128(const void *prev, void *next, const void *packed,
+                             const LayerArgs &a, uint32_t grid, hipStream_t s);
+hipError_t launch_readout_c128(const void *last, void *result, hipStream_t s);
+
+// Integer path: `rp` primes share the sweep; tables are rp planes of `plane`
+// entries each.  `red` holds rp reduced copies of the matrix (rp * n * n).
+hipError_t launch_reduce_modp(const int64_t *a_dev, int n, const uint64_t *primes, int rp,
+                              uint64_t *red, uint64_t *layer1, size_t plane, hipStream_t s);
+hipError_t launch_layer_modp(const uint64_t *prev, uint64_t *next, size_t plane,
+                             const uint64_t *red, const uint64_t *primes, int rp,
+                             const LayerArgs &a, uint32_t grid, hipStream_t s);
+hipError_t launch_readout_modp(const uint64_t *last, size_t plane, int rp, uint64_t *out,
+                               hipStream_t s);
+
+// ---- batched on-chip kernel (perm_batch.hip) ----
+struct BatchChunk {
+    uint32_t first;   // index into the sorted order
+    uint16_t count;   // matrices in this chunk (same n)
+    uint8_t n;
+    uint8_t group;    // log2 of threads per matrix
+};
+
+hipError_t launch_batch_reset(uint32_t *counter, hipStream_t s);
+hipError_t launch_batch_c128(const void *mats, const int64_t *offsets, const uint32_t *order,
+                             const BatchChunk *chunks, uint32_t nchunks, uint32_t *counter,
+                             void *results, int nmax, int grid, hipStream_t s);
+hipError_t launch_batch_modp(const int64_t *mats, const int64_t *offsets, const uint32_t *order,
+                             const BatchChunk *chunks, uint32_t nchunks, uint32_t *counter,
+                             const uint64_t *primes, int nprimes, uint64_t *res, uint32_t count,
+                             int nmax, int grid, hipStream_t s);
+size_t batch_lds_bytes(int nmax, int elem_bytes);
+int batch_blocks_per_cu(int nmax, int elem_bytes);
+
+}  // namespace permgpu

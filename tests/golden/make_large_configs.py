@@ -1,0 +1,75 @@
+"""Write tests/golden/large_configs.json: oracle results for the full-size
+workloads, so GPU parity tests at those sizes need not rerun the oracle.
+
+Calls only the oracle (oracle/) and the seeded input generators:
+    python tests/golden/make_large_configs.py [--threads N]
+
+Entries (inputs are regenerated from the seeds by the tests):
+  c128_n26_s{0,1}  26x26 complex Gaussian (parts N(0, 1/2)), seeds 0, 1
+  c128_n28_s0      28x28 complex Gaussian, seed 0
+  int_n30_bern_s0  30x30 Bernoulli(1/2) 0/1 matrix, seed 0 (exact integer)
+  int_n10_u09_s*   10x10 uniform {0..9}, seeds 0..15 (exact integer)
+Complex values are stored as the IEEE-754 bit patterns of the oracle's fp64
+FMA chain, plus the oracle's per(|A|) for the relative tolerance.
+"""
+import argparse
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.dirname(os.path.dirname(os.path.abspath(__file__))))
+sys.path.insert(0, ROOT)
+
+import numpy as np  # noqa: E402
+
+from oracle import native  # noqa: E402
+from paper_1802_02779_amd import inputs  # noqa: E402
+
+OUT = os.path.join(os.path.dirname(os.path.abspath(__file__)), "large_configs.json")
+
+
+def c128_entry(A, threads):
+    t0 = time.time()
+    bits = native.per_c128_bits(A, mode=native.MODE_LAYERS, nthreads=threads)
+    pa = native.per_abs(A, nthreads=threads)
+    return {"re_bits": f"0x{int(bits[0]):016x}", "im_bits": f"0x{int(bits[1]):016x}",
+            "value": [float(np.array([bits[0]], dtype=np.uint64).view(np.float64)[0]),
+                      float(np.array([bits[1]], dtype=np.uint64).view(np.float64)[0])],
+            "per_abs": pa, "oracle_seconds": round(time.time() - t0, 2)}
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--threads", type=int, default=0)
+    ap.add_argument("--only", default="")
+    args = ap.parse_args()
+    data = {}
+    if os.path.exists(OUT):
+        with open(OUT) as f:
+            data = json.load(f)
+    jobs = [
+        ("int_n10_u09_s%d" % s, lambda s=s: {"value": str(native.per_int(inputs.uniform_int(10, 0, 9, seed=s)))})
+        for s in range(16)
+    ]
+    jobs += [
+        ("c128_n26_s0", lambda: c128_entry(inputs.complex_gaussian(26, seed=0), args.threads)),
+        ("c128_n26_s1", lambda: c128_entry(inputs.complex_gaussian(26, seed=1), args.threads)),
+        ("c128_n28_s0", lambda: c128_entry(inputs.complex_gaussian(28, seed=0), args.threads)),
+        ("int_n30_bern_s0", lambda: {"value": str(native.per_int(inputs.bernoulli01(30, seed=0),
+                                                                  nthreads=args.threads))}),
+    ]
+    for key, fn in jobs:
+        if args.only and args.only not in key:
+            continue
+        if key in data:
+            continue
+        t0 = time.time()
+        data[key] = fn()
+        print(f"{key}: {data[key]}  ({time.time() - t0:.1f}s)", flush=True)
+        with open(OUT, "w") as f:
+            json.dump(data, f, indent=1, sort_keys=True)
+
+
+if __name__ == "__main__":
+    main()

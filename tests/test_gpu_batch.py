@@ -1,0 +1,123 @@
+"""GPU parity of perm_solve_batch (persistent on-chip kernel, graph replay)."""
+import numpy as np
+import pytest
+
+from oracle import exact, native
+from paper_1802_02779_amd import inputs
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def P():
+    import torch
+    assert torch.cuda.is_available(), "GPU tests need a GPU"
+    from paper_1802_02779_amd import perm
+    perm.lib()
+    return perm
+
+
+def c_bits_arr(z):
+    z = np.ascontiguousarray(np.asarray(z, dtype=np.complex128))
+    return z.view(np.uint64).reshape(-1, 2)
+
+
+def run_batch(P, batch, flags=0, ws=None, results=None):
+    import torch
+    d_mats = torch.from_numpy(batch.mats).cuda()
+    if results is None:
+        results = torch.zeros(batch.count, dtype=torch.complex128, device="cuda")
+    if ws is None:
+        ws = P.device_buffer(P.perm_batch_workspace_bytes(P.PERM_COMPLEX128, batch.ns))
+    P.perm_solve_batch(P.PERM_COMPLEX128, batch.ns, batch.offsets, d_mats, results, ws,
+                       flags=flags | P.PERM_BATCH_SYNC)
+    return results.cpu().numpy(), d_mats, results, ws
+
+
+def oracle_bits(batch):
+    out = np.empty(batch.count, dtype=np.complex128)
+    for i in range(batch.count):
+        out[i] = native.per_c128(batch.matrix(i), mode=native.MODE_MEMO)
+    return c_bits_arr(out)
+
+
+def test_batch_mixed_orders_bitwise(P):
+    U = inputs.haar_unitary(64, seed=11)
+    b = inputs.submatrix_batch(U, 3000, 0, 12, seed=1)
+    print("[gpu] batch 3000 mixed n=0..12", flush=True)
+    got, *_ = run_batch(P, b)
+    assert (c_bits_arr(got) == oracle_bits(b)).all()
+
+
+def test_batch_equals_single_solve(P):
+    U = inputs.haar_unitary(64, seed=12)
+    b = inputs.submatrix_batch(U, 200, 3, 12, seed=2)
+    got, *_ = run_batch(P, b)
+    for i in range(0, 200, 7):
+        assert (c_bits_arr([P.perm_solve(b.matrix(i))]) == c_bits_arr([got[i]])).all()
+
+
+def test_batch_single_order_each(P):
+    U = inputs.haar_unitary(64, seed=13)
+    for n in range(0, 13):
+        b = inputs.submatrix_batch(U, 97, n, n, seed=n)
+        got, *_ = run_batch(P, b)
+        assert (c_bits_arr(got) == oracle_bits(b)).all(), n
+
+
+def test_batch_graph_replays(P):
+    import torch
+    U = inputs.haar_unitary(64, seed=14)
+    b = inputs.submatrix_batch(U, 5000, 3, 12, seed=3)
+    ref = oracle_bits(b)
+    got, d_mats, results, ws = run_batch(P, b, flags=P.PERM_BATCH_GRAPH)
+    assert (c_bits_arr(got) == ref).all()
+    for rep in range(4):
+        results.zero_()  # eager work between replays
+        torch.cuda.synchronize()
+        P.perm_solve_batch(P.PERM_COMPLEX128, b.ns, b.offsets, d_mats, results, ws,
+                           flags=P.PERM_BATCH_GRAPH | P.PERM_BATCH_REUSE | P.PERM_BATCH_SYNC)
+        assert (c_bits_arr(results.cpu().numpy()) == ref).all(), rep
+
+
+def test_batch_group_variants(P):
+    U = inputs.haar_unitary(64, seed=15)
+    b = inputs.submatrix_batch(U, 600, 3, 12, seed=4)
+    ref = oracle_bits(b)
+    saved = P.perm_tuning_get()
+    try:
+        for g in (16, 32, 64, 128, 256):
+            t = P.perm_tuning_t.from_buffer_copy(saved)
+            for n in range(13):
+                t.batch_group[n] = g
+            P.perm_tuning_set(t)
+            got, *_ = run_batch(P, b)
+            assert (c_bits_arr(got) == ref).all(), g
+    finally:
+        P.perm_tuning_set(saved)
+
+
+def test_batch_empty(P):
+    import torch
+    ws = P.device_buffer(256)
+    res = torch.zeros(1, dtype=torch.complex128, device="cuda")
+    P.perm_solve_batch(P.PERM_COMPLEX128, np.zeros(0, np.int32), np.zeros(0, np.int64),
+                       res, res, ws, flags=P.PERM_BATCH_SYNC)
+
+
+def test_batch_int64(P):
+    rng = np.random.default_rng(21)
+    ns = rng.integers(0, 13, size=300).astype(np.int32)
+    offsets = np.zeros(300, dtype=np.int64)
+    offsets[1:] = np.cumsum(ns.astype(np.int64) ** 2)[:-1]
+    mats = np.empty(int((ns.astype(np.int64) ** 2).sum()), dtype=np.int64)
+    for i, n in enumerate(ns):
+        lo, hi = (-(2 ** 63), 2 ** 63 - 1) if i % 5 == 0 else (-50, 50)
+        mats[offsets[i]:offsets[i] + n * n] = rng.integers(lo, hi, size=n * n, dtype=np.int64, endpoint=True)
+    ws = P.device_buffer(P.perm_batch_workspace_bytes(P.PERM_INT64, ns))
+    print("[gpu] int batch 300", flush=True)
+    got = P.perm_solve_batch(P.PERM_INT64, ns, offsets, mats, None, ws)
+    for i, n in enumerate(ns):
+        A = mats[offsets[i]:offsets[i] + n * n].reshape(n, n)
+        ref = exact.per_definition(A) if n <= 6 else native.per_int(A)
+        assert got[i] == ref, (i, n)

@@ -1,0 +1,253 @@
+"""GPU parity of perm_solve / perm_solve_async against the oracle.
+
+Complex results are compared bit for bit with the oracle's fp64 FMA chain
+(both evaluate every stored sub-permanent with the same chain, so any
+difference is a bug) and, as the stated gate, within 1e-10 * per(|A|).
+Integer results are exact.  Full-size workloads compare against values the
+oracle wrote into tests/golden/large_configs.json.
+"""
+import json
+import math
+import os
+
+import numpy as np
+import pytest
+
+from oracle import exact, native
+from paper_1802_02779_amd import inputs
+
+pytestmark = pytest.mark.gpu
+
+GOLDEN = os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden", "large_configs.json")
+TOL = 1e-10
+
+
+@pytest.fixture(scope="module")
+def P():
+    import torch
+    assert torch.cuda.is_available(), "GPU tests need a GPU"
+    from paper_1802_02779_amd import perm
+    perm.lib()
+    return perm
+
+
+@pytest.fixture(scope="module")
+def golden():
+    with open(GOLDEN) as f:
+        return json.load(f)
+
+
+def c_bits(z):
+    return tuple(int(x) for x in np.array([z.real, z.imag], dtype=np.float64).view(np.uint64))
+
+
+def check_complex(P, A, label=""):
+    print(f"[gpu] complex n={A.shape[0]} {label}", flush=True)
+    z = P.perm_solve(A)
+    ref = native.per_c128(A)
+    assert c_bits(z) == c_bits(ref), (label, z, ref)
+    assert abs(z - ref) <= TOL * native.per_abs(A)
+    return z
+
+
+# ----------------------------------------------------------- complex128
+@pytest.mark.parametrize("n", list(range(2, 19)) + [20, 22])
+def test_complex_gaussian_bitwise(P, n):
+    seeds = range(3) if n <= 16 else range(1)
+    for s in seeds:
+        check_complex(P, inputs.complex_gaussian(n, seed=100 * n + s), f"seed={s}")
+
+
+@pytest.mark.parametrize("n", [3, 5, 8])
+def test_complex_vs_exact_definition(P, n):
+    A = inputs.complex_gaussian(n, seed=n)
+    ref = exact.per_definition(A)
+    z = P.perm_solve(A)
+    d = abs(z - ref.to_complex())
+    assert d <= 1e-14 * native.per_abs(A) + 1e-300
+
+
+def test_complex_dyadic_exact_value(P):
+    # parts are multiples of 2^-20: the exact permanent is a known rational
+    A = inputs.dyadic_complex(10, seed=3, bits=20)
+    ref = exact.per_ryser(exact.as_exact_matrix(A)).to_complex()
+    z = P.perm_solve(A)
+    assert abs(z - ref) <= 1e-13 * native.per_abs(A)
+
+
+def test_complex_haar_submatrices(P):
+    U = inputs.haar_unitary(64, seed=7)
+    rng = np.random.default_rng(7)
+    for n in (5, 9, 14, 19):
+        r = rng.permutation(64)[:n]
+        c = rng.permutation(64)[:n]
+        check_complex(P, np.ascontiguousarray(U[np.ix_(r, c)]), "haar")
+
+
+def test_complex_lda_and_async(P):
+    import torch
+    n = 17
+    big = inputs.complex_gaussian(24, seed=9)
+    A = np.ascontiguousarray(big[:n, :n])
+    z = check_complex(P, A, "packed")
+    # host call with lda > n through the raw ABI
+    import ctypes
+    L = P.lib()
+    ws = P.device_buffer(P.perm_workspace_bytes(P.PERM_COMPLEX128, n))
+    out = P.perm_c128_t()
+    big = np.ascontiguousarray(big)
+    rc = L.perm_solve(1, n, big.ctypes.data, 24, ctypes.byref(out), ws.data_ptr(), ws.numel(),
+                      torch.cuda.current_stream().cuda_stream)
+    assert rc == 0
+    assert c_bits(complex(out.re, out.im)) == c_bits(z)
+    # device input with lda = 24, device output
+    d_big = torch.from_numpy(big).cuda()
+    d_res = torch.zeros(1, dtype=torch.complex128, device="cuda")
+    P.perm_solve_async(n, d_big, 24, d_res, ws)
+    torch.cuda.synchronize()
+    assert c_bits(complex(d_res.cpu().numpy()[0])) == c_bits(z)
+
+
+def test_complex_trivial_orders_async(P):
+    import torch
+    ws = P.device_buffer(256)
+    res = torch.zeros(1, dtype=torch.complex128, device="cuda")
+    P.perm_solve_async(0, None, 1, res, ws)
+    torch.cuda.synchronize()
+    assert complex(res.cpu().numpy()[0]) == 1
+    a = torch.tensor([[3.0 - 2.0j]], dtype=torch.complex128, device="cuda")
+    P.perm_solve_async(1, a, 1, res, ws)
+    torch.cuda.synchronize()
+    assert complex(res.cpu().numpy()[0]) == 3.0 - 2.0j
+    assert P.perm_solve(np.array([[1 + 1j, 2], [3, 4j]])) == (1 + 1j) * 4j + 2 * 3
+
+
+def test_workspace_too_small(P):
+    n = 12
+    ws = P.device_buffer(P.perm_workspace_bytes(P.PERM_COMPLEX128, n) - 1)
+    with pytest.raises(P.PermError) as e:
+        P.perm_solve(inputs.complex_gaussian(n, seed=1), workspace=ws)
+    assert e.value.code == P.PERM_ENOMEM
+
+
+def test_complex_invariances(P):
+    n = 20
+    A = inputs.complex_gaussian(n, seed=21)
+    z = P.perm_solve(A)
+    pa = native.per_abs(A)
+    rng = np.random.default_rng(3)
+    for B in (A[rng.permutation(n)], A[:, rng.permutation(n)], np.ascontiguousarray(A.T)):
+        assert abs(P.perm_solve(np.ascontiguousarray(B)) - z) <= 1e-12 * pa
+    # power-of-two scaling of one row or column is exact: bitwise
+    B = A.copy()
+    B[7] *= 4.0
+    C = A.copy()
+    C[:, 11] *= 0.5
+    assert c_bits(P.perm_solve(B)) == c_bits(z * 4.0)
+    assert c_bits(P.perm_solve(C)) == c_bits(z * 0.5)
+    D = A.copy()
+    D[13] = 0
+    assert P.perm_solve(D) == 0
+
+
+def test_complex_rank_one_large(P):
+    n = 28
+    rng = np.random.default_rng(28)
+    u = np.exp(1j * rng.uniform(0, 2 * np.pi, n)) * rng.uniform(0.8, 1.2, n)
+    v = np.exp(1j * rng.uniform(0, 2 * np.pi, n)) * rng.uniform(0.8, 1.2, n)
+    A = np.outer(u, v)
+    z = P.perm_solve(A)
+    ref = math.factorial(n) * np.prod(u) * np.prod(v)
+    assert abs(z - ref) <= 1e-12 * abs(ref)
+
+
+def test_determinism_and_tuning_variants(P):
+    n = 20
+    A = inputs.complex_gaussian(n, seed=5)
+    ref = c_bits(native.per_c128(A))
+    saved = P.perm_tuning_get()
+    try:
+        for t in range(3, 16):
+            for remap in (0, 1):
+                tu = P.perm_tuning_t.from_buffer_copy(saved)
+                tu.layer_t[n] = t
+                tu.layer_xcd_remap[n] = remap
+                P.perm_tuning_set(tu)
+                assert c_bits(P.perm_solve(A)) == ref, (t, remap)
+    finally:
+        P.perm_tuning_set(saved)
+    for _ in range(5):
+        assert c_bits(P.perm_solve(A)) == ref
+
+
+# --------------------------------------------------------- full sizes
+@pytest.mark.parametrize("key,n,seed", [("c128_n26_s0", 26, 0), ("c128_n26_s1", 26, 1),
+                                        ("c128_n28_s0", 28, 0)])
+def test_full_size_complex(P, golden, key, n, seed):
+    g = golden[key]
+    A = inputs.complex_gaussian(n, seed=seed)
+    print(f"[gpu] full size {key}", flush=True)
+    z = P.perm_solve(A)
+    assert c_bits(z) == (int(g["re_bits"], 16), int(g["im_bits"], 16)), (z, g["value"])
+    assert abs(z - complex(*g["value"])) <= TOL * g["per_abs"]
+
+
+# ------------------------------------------------------------- int64
+@pytest.mark.parametrize("n", list(range(2, 15)) + [16, 18, 20])
+def test_int_random(P, n):
+    print(f"[gpu] int n={n}", flush=True)
+    A = inputs.uniform_int(n, -99, 99, seed=n)
+    assert P.perm_solve(A) == native.per_int(A)
+
+
+@pytest.mark.parametrize("n", [2, 5, 8, 11])
+def test_int_huge_entries(P, n):
+    rng = np.random.default_rng(1000 + n)
+    A = rng.integers(-(2 ** 63), 2 ** 63 - 1, size=(n, n), dtype=np.int64, endpoint=True)
+    ref = exact.per_definition(A) if n <= 8 else native.per_int(A)
+    assert P.perm_solve(A) == ref
+
+
+def test_int_config_n10(P, golden):
+    for s in range(16):
+        A = inputs.uniform_int(10, 0, 9, seed=s)
+        assert P.perm_solve(A) == int(golden[f"int_n10_u09_s{s}"]["value"])
+
+
+def test_int_full_size_bernoulli_n30(P, golden):
+    print("[gpu] int n=30 Bernoulli", flush=True)
+    A = inputs.bernoulli01(30, seed=0)
+    assert P.perm_solve(A) == int(golden["int_n30_bern_s0"]["value"])
+
+
+def test_int_closed_forms_n30(P):
+    n = 30
+    J = np.ones((n, n), dtype=np.int64)
+    I = np.eye(n, dtype=np.int64)
+    d = [1, 0]
+    for k in range(2, n + 1):
+        d.append((k - 1) * (d[-1] + d[-2]))
+    print("[gpu] int n=30 closed forms", flush=True)
+    assert P.perm_solve(J) == math.factorial(n) == 265252859812191058636308480000000
+    assert P.perm_solve(J - I) == d[n] == 97581073836835777732377428235481
+    assert P.perm_solve(I) == 1
+    assert P.perm_solve(-J) == math.factorial(n)  # (-1)^30 * 30!
+    T = np.triu(inputs.uniform_int(n, 1, 3, seed=4))
+    assert P.perm_solve(T) == math.prod(int(x) for x in np.diag(T))
+
+
+def test_int_invariances_and_small_workspace(P):
+    n = 18
+    A = inputs.uniform_int(n, -30, 30, seed=8)
+    ref = native.per_int(A)
+    rng = np.random.default_rng(2)
+    assert P.perm_solve(np.ascontiguousarray(A[rng.permutation(n)])) == ref
+    assert P.perm_solve(np.ascontiguousarray(A[:, rng.permutation(n)])) == ref
+    assert P.perm_solve(np.ascontiguousarray(A.T)) == ref
+    B = A.copy()
+    B[3] *= -5
+    assert P.perm_solve(B) == -5 * ref
+    # a workspace that holds one prime's tables only: more sweeps, same value
+    from math import comb
+    one = P.perm_workspace_bytes(P.PERM_INT64, n) - 2 * 2 * 8 * max(comb(n, k) for k in range(n + 1)) + 1024
+    assert P.perm_solve(A, workspace=P.device_buffer(one)) == ref
