@@ -1,0 +1,302 @@
+"""Benchmark of the Store-zechin permanent on one MI355X.
+
+    python bench.py [--gpus 1] [--steps K] [--warmup W] [--no-cpu-baseline] [--no-extras]
+
+One step is one complete permanent of a 28x28 complex128 matrix (iid complex
+Gaussian entries, parts N(0, 1/2)): ingest of the device-resident matrix,
+layer 1, the 27 layer sweeps and the readout, all in the library's kernels
+(perm_solve_async).  The timed region holds exactly K steps between two
+device synchronizations; the input is already in HBM.  The JSON line on
+stdout reports perms/s, the roofline of the dominant kernel (the complex
+layer sweep) measured with HIP events on its own stream, and the oracle timed
+on the host's cores.  Extra fields cover the other workloads: the 26x26
+complex and 30x30 0/1 integer solves, the 10x10 integer solve, the batched
+2^20 submatrix workload against a plain per-matrix loop, and the serving
+trace.  Progress goes to stderr.
+"""
+from __future__ import annotations
+
+import argparse
+import hashlib
+import json
+import math
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+METRIC = "n=28 complex128 perm wall time; batched perms/s; p50/p99 latency vs plain"
+HBM_PEAK_GBS = 8000.0
+FP64_PEAK_TFLOPS = 78.6
+GOLDEN = os.path.join(ROOT, "tests", "golden", "large_configs.json")
+COUNTERS = os.path.join(ROOT, "profiles", "layer_c128_n28_counters.json")
+
+
+def log(*a):
+    print("[bench]", *a, file=sys.stderr, flush=True)
+
+
+def layer_bytes(n: int, elem: int = 16) -> int:
+    """Algorithmic HBM bytes of all layer sweeps of one order-n permanent:
+    every stored value of layers 1..n-1 read once, of layers 2..n written once."""
+    return elem * sum(math.comb(n, k - 1) + math.comb(n, k) for k in range(2, n + 1))
+
+
+def algorithmic_flops(n: int) -> int:
+    """6 flops per complex multiplication, 2 per complex addition; a stored
+    value of order k costs k multiplications and k-1 additions."""
+    M = sum(k * math.comb(n, k) for k in range(2, n + 1))
+    A = sum((k - 1) * math.comb(n, k) for k in range(2, n + 1))
+    return 6 * M + 2 * A
+
+
+def source_hash() -> str:
+    h = hashlib.sha256()
+    for f in ("perm_layers.hip", "perm_internal.h"):
+        with open(os.path.join(ROOT, "paper_1802_02779_amd", "csrc", f), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()[:16]
+
+
+def bits(z):
+    import numpy as np
+    return tuple(int(x) for x in np.array([z.real, z.imag], dtype=np.float64).view(np.uint64))
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-extras", action="store_true")
+    ap.add_argument("--copy-calibration", action="store_true",
+                    help="first copy 1 GiB device to device (a plain copy kernel of known size, "
+                         "the reference for HBM byte counters)")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print(f"bench.py measures one GPU only (asked for --gpus {args.gpus}); the library runs a "
+              "permanent on a single MI355X and has no multi-GPU path.", file=sys.stderr)
+        sys.exit(2)
+
+    import numpy as np
+    import torch
+
+    from paper_1802_02779_amd import inputs, perm
+
+    torch.cuda.set_device(0)
+    perm.lib()
+    C128 = perm.PERM_COMPLEX128
+    if args.copy_calibration:
+        src = torch.empty(1 << 30, dtype=torch.uint8, device="cuda")
+        dst = torch.empty_like(src)
+        dst.copy_(src)
+        torch.cuda.synchronize()
+        del src, dst
+    golden = {}
+    if os.path.exists(GOLDEN):
+        with open(GOLDEN) as f:
+            golden = json.load(f)
+
+    # ------------------------------------------------ headline: n = 28
+    n = 28
+    A = inputs.complex_gaussian(n, seed=0)
+    d_a = torch.from_numpy(A).cuda()
+    d_res = torch.zeros(1, dtype=torch.complex128, device="cuda")
+    ws = perm.device_buffer(perm.perm_workspace_bytes(C128, n))
+    log(f"n={n} complex128: workspace {ws.numel() / 1e9:.2f} GB, warmup {args.warmup}")
+    for _ in range(args.warmup):
+        perm.perm_solve_async(n, d_a, n, d_res, ws)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        perm.perm_solve_async(n, d_a, n, d_res, ws)
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    ms_per_step = (t1 - t0) * 1000.0 / args.steps
+    z = complex(d_res.cpu().numpy()[0])
+    key = "c128_n28_s0"
+    verified = (bits(z) == (int(golden[key]["re_bits"], 16), int(golden[key]["im_bits"], 16))) \
+        if key in golden else None
+    log(f"n=28: {ms_per_step:.3f} ms/step over {args.steps} steps, verified={verified}")
+
+    # per-kernel durations: HIP events around every layer launch on the
+    # stream the library launches on (separate pass, same work)
+    perm.perm_profile_enable(True)
+    perm.perm_profile_read()
+    for _ in range(args.steps):
+        perm.perm_solve_async(n, d_a, n, d_res, ws)
+    torch.cuda.synchronize()
+    prof = perm.perm_profile_read()
+    perm.perm_profile_enable(False)
+    launches = int(prof.layer_c128_launches)
+    avg_ms = prof.layer_c128_ms / max(launches, 1)
+    bytes_per_launch = layer_bytes(n) / (n - 1)
+    achieved = bytes_per_launch / (avg_ms * 1e-3) / 1e9
+    flops_per_step = algorithmic_flops(n)
+    kern_ms_per_step = prof.layer_c128_ms / args.steps
+    traffic = None
+    if os.path.exists(COUNTERS):
+        with open(COUNTERS) as f:
+            cnt = json.load(f)
+        if cnt.get("source_hash") == source_hash():
+            traffic = cnt.get("hbm_bytes_per_launch")
+    roofline = {"bound": "hbm", "kernel": "k_layer_c128", "achieved": round(achieved, 1),
+                "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
+                "traffic": traffic, "avg_launch_ms": round(avg_ms, 5), "launches_per_step": n - 1,
+                "algorithmic_bytes_per_launch": int(bytes_per_launch),
+                "fp64_tflops": round(flops_per_step / (kern_ms_per_step * 1e-3) / 1e12, 3),
+                "fp64_frac": round(flops_per_step / (kern_ms_per_step * 1e-3) / 1e12 / FP64_PEAK_TFLOPS, 4)}
+    log(f"layer sweep: avg {avg_ms:.4f} ms/launch, {achieved:.0f} GB/s algorithmic")
+
+    result = {
+        "metric": METRIC, "value": round(1000.0 / ms_per_step, 3), "unit": "perms/s", "n_gpus": 1,
+        "steps": args.steps, "warmup": args.warmup, "ms_per_step": round(ms_per_step, 4),
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f64",
+        "data": "synthetic",
+        "config": {"workload": "one 28x28 complex128 permanent per step, entries iid complex Gaussian "
+                               "(parts N(0,1/2)), seed 0, device-resident input",
+                   "n": n, "global_batch": 1, "parallelism": "single GPU"},
+        "verified_bitwise_vs_oracle": verified,
+        "roofline": roofline,
+    }
+
+    if not args.no_extras:
+        result["extras"] = extras(perm, inputs, golden, np, torch, log)
+
+    if not args.no_cpu_baseline:
+        result["cpu_baseline"] = cpu_baseline(inputs, log)
+    print(json.dumps(result), flush=True)
+
+
+def extras(perm, inputs, golden, np, torch, log):
+    C128 = perm.PERM_COMPLEX128
+    out = {}
+    # configs: 26x26 complex
+    n = 26
+    A = inputs.complex_gaussian(n, seed=0)
+    d_a = torch.from_numpy(A).cuda()
+    d_res = torch.zeros(1, dtype=torch.complex128, device="cuda")
+    ws = perm.device_buffer(perm.perm_workspace_bytes(C128, n))
+    perm.perm_solve_async(n, d_a, n, d_res, ws)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(10):
+        perm.perm_solve_async(n, d_a, n, d_res, ws)
+    torch.cuda.synchronize()
+    ms = (time.perf_counter() - t0) * 100.0
+    z = complex(d_res.cpu().numpy()[0])
+    g = golden.get("c128_n26_s0")
+    out["c128_n26"] = {"ms": round(ms, 4), "roofline_ms_hbm": round(layer_bytes(26) / HBM_PEAK_GBS / 1e6, 4),
+                       "verified": (bits(z) == (int(g["re_bits"], 16), int(g["im_bits"], 16))) if g else None}
+    log(f"n=26 complex: {ms:.3f} ms")
+    del ws
+
+    # host-to-host n = 28 (PCIe-inclusive, for the record)
+    A28 = inputs.complex_gaussian(28, seed=0)
+    ws = perm.device_buffer(perm.perm_workspace_bytes(C128, 28))
+    perm.perm_solve(A28, workspace=ws)
+    t0 = time.perf_counter()
+    for _ in range(5):
+        perm.perm_solve(A28, workspace=ws)
+    out["c128_n28_host_to_host_ms"] = round((time.perf_counter() - t0) * 200.0, 4)
+    del ws
+
+    # 30x30 Bernoulli 0/1, exact (3 primes: 2 + 1 redundant)
+    B = inputs.bernoulli01(30, seed=0)
+    wsi = perm.device_buffer(perm.perm_workspace_bytes(perm.PERM_INT64, 30))
+    v = perm.perm_solve(B, workspace=wsi)
+    t0 = time.perf_counter()
+    reps = 3
+    for _ in range(reps):
+        v = perm.perm_solve(B, workspace=wsi)
+    ms = (time.perf_counter() - t0) * 1000.0 / reps
+    g = golden.get("int_n30_bern_s0")
+    out["int_n30_bernoulli"] = {"ms": round(ms, 3), "value": str(v),
+                                "verified": (str(v) == g["value"]) if g else None,
+                                "hbm_bytes": layer_bytes(30, 8 * 3)}
+    log(f"n=30 0/1 integer: {ms:.2f} ms")
+    del wsi
+
+    # 10x10 uniform {0..9} integer, host to host
+    C = inputs.uniform_int(10, 0, 9, seed=0)
+    wsc = perm.device_buffer(perm.perm_workspace_bytes(perm.PERM_INT64, 10))
+    perm.perm_solve(C, workspace=wsc)
+    ts = []
+    for _ in range(200):
+        t0 = time.perf_counter()
+        perm.perm_solve(C, workspace=wsc)
+        ts.append(time.perf_counter() - t0)
+    out["int_n10_us_median"] = round(float(np.median(ts)) * 1e6, 2)
+
+    # batched: 2^20 submatrices of a 64x64 Haar unitary, n uniform in 3..12
+    count = 1 << 20
+    U = inputs.haar_unitary(64, seed=2018)
+    t0 = time.perf_counter()
+    b = inputs.submatrix_batch(U, count, 3, 12, seed=1)
+    log(f"batch input generated in {time.perf_counter() - t0:.1f}s ({b.mats.nbytes / 1e9:.2f} GB)")
+    d_mats = torch.from_numpy(b.mats).cuda()
+    d_out = torch.zeros(count, dtype=torch.complex128, device="cuda")
+    wsb = perm.device_buffer(perm.perm_batch_workspace_bytes(C128, b.ns))
+    flags = perm.PERM_BATCH_GRAPH
+    perm.perm_solve_batch(C128, b.ns, b.offsets, d_mats, d_out, wsb, flags=flags | perm.PERM_BATCH_SYNC)
+    times = []
+    for _ in range(7):
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        perm.perm_solve_batch(C128, b.ns, b.offsets, d_mats, d_out, wsb,
+                              flags=flags | perm.PERM_BATCH_REUSE | perm.PERM_BATCH_SYNC)
+        times.append(time.perf_counter() - t0)
+    med = float(np.median(times))
+    flops = 0
+    cnts = np.bincount(b.ns, minlength=13)
+    for n in range(3, 13):
+        flops += int(cnts[n]) * algorithmic_flops(n)
+    perm.perm_profile_enable(True)
+    perm.perm_profile_read()
+    perm.perm_solve_batch(C128, b.ns, b.offsets, d_mats, d_out, wsb,
+                          flags=flags | perm.PERM_BATCH_REUSE | perm.PERM_BATCH_SYNC)
+    pb = perm.perm_profile_read()
+    perm.perm_profile_enable(False)
+    # plain: the same matrices one perm_solve_async at a time (first 4096)
+    nplain = 4096
+    d_one = torch.zeros(1, dtype=torch.complex128, device="cuda")
+    wsp = perm.device_buffer(perm.perm_workspace_bytes(C128, 12))
+    views = [d_mats[int(b.offsets[i]):int(b.offsets[i]) + int(b.ns[i]) ** 2] for i in range(nplain)]
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for i in range(nplain):
+        perm.perm_solve_async(int(b.ns[i]), views[i], int(b.ns[i]), d_one, wsp)
+    torch.cuda.synchronize()
+    plain_rate = nplain / (time.perf_counter() - t0)
+    out["batch_2p20"] = {"perms_per_s": round(count / med, 1), "ms": round(med * 1000, 3),
+                         "kernel_ms": round(pb.batch_ms, 3),
+                         "fp64_tflops_kernel": round(flops / (pb.batch_ms * 1e-3) / 1e12, 3),
+                         "fp64_frac_kernel": round(flops / (pb.batch_ms * 1e-3) / 1e12 / FP64_PEAK_TFLOPS, 4),
+                         "plain_perm_solve_perms_per_s": round(plain_rate, 1),
+                         "speedup_vs_plain": round(count / med / plain_rate, 1),
+                         "launch": "graph replay of one persistent kernel"}
+    log(f"batch 2^20: {med * 1000:.2f} ms ({count / med:.3e} perms/s); plain {plain_rate:.0f} perms/s")
+    del d_mats, d_out, wsb
+    return out
+
+
+def cpu_baseline(inputs, log):
+    from oracle import native
+    native.build(force=False)
+    A = inputs.complex_gaussian(28, seed=0)
+    cores = native.max_threads()
+    log(f"oracle (C, layers mode) on {cores} host threads, one 28x28 complex permanent ...")
+    t0 = time.perf_counter()
+    native.per_c128(A, mode=native.MODE_LAYERS, nthreads=0)
+    dt = time.perf_counter() - t0
+    log(f"oracle: {dt:.1f} s")
+    return {"value": round(1.0 / dt, 5), "unit": "perms/s", "cores": cores, "kind": "oracle",
+            "sample": "one full 28x28 complex128 permanent (all 2^28 stored sub-permanents), "
+                      f"{dt:.1f} s wall"}
+
+
+if __name__ == "__main__":
+    main()

@@ -195,13 +195,20 @@ int perm_server_destroy(perm_server_t *s);
 
 /* ------------------------------------------------------ tuning / stats --- */
 
-/* Tile and schedule parameters.  layer_t: columns per low window of the
- * layer sweep for order n (the others form the tile's fixed high part);
- * batch_group: threads that share one matrix in the batched kernel. */
+/* Tile and schedule parameters (none of them changes any result bit).
+ *   layer_t[n]         columns of the low window of the layer sweep for order
+ *                      n (the other columns form a tile's fixed high part);
+ *                      0 = library default.
+ *   layer_xcd_remap[n] tiles dealt to each of the 8 XCDs in runs of this many
+ *                      consecutive tiles; 0 = hardware order, -1 = default.
+ *   layer_flags[n]     bit 0: non-temporal stores of layer outputs.
+ *   batch_group[n]     threads that share one matrix in the batched kernel
+ *                      (power of two, 16..256); 0 = library default. */
 typedef struct {
-    int layer_t[PERM_N_MAX + 1];          /* 0 = library default */
-    int layer_xcd_remap[PERM_N_MAX + 1];  /* -1 = default, 0/1 = off/on */
-    int batch_group[PERM_BATCH_N_MAX + 1];/* 0 = library default */
+    int layer_t[PERM_N_MAX + 1];
+    int layer_xcd_remap[PERM_N_MAX + 1];
+    int layer_flags[PERM_N_MAX + 1];
+    int batch_group[PERM_BATCH_N_MAX + 1];
 } perm_tuning_t;
 
 /* Read / replace the process-wide tuning table (values are validated;

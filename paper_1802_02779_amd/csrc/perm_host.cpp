@@ -292,7 +292,13 @@ int tuned_layer_remap(int n) {
     std::lock_guard<std::mutex> lk(g_tune_mu);
     tune_init_locked();
     const int r = g_tune.layer_xcd_remap[n];
-    return r < 0 ? 1 : r;
+    return r >= 0 ? r : (n >= 20 ? 64 : 0);
+}
+
+int tuned_layer_flags(int n) {
+    std::lock_guard<std::mutex> lk(g_tune_mu);
+    tune_init_locked();
+    return g_tune.layer_flags[n];
 }
 
 // Threads per matrix in the batched kernel: a power of two in [16, 256]
@@ -379,12 +385,13 @@ int solve_c128_device(int n, const void *a_dev, int64_t lda, void *result_dev, v
     char *buf1 = buf0 + lay;
     HIPCALL(launch_pack_c128(a_dev, lda, n, packed, buf0, s), "pack kernel");
     const int t = tuned_layer_t(n);
-    const int remap = tuned_layer_remap(n);
+    const int chunk = tuned_layer_remap(n);
+    const int nt = tuned_layer_flags(n) & 1;
     const bool prof = profiling_on();
     char *prev = buf0, *next = buf1;
     for (int k = 2; k <= n; k++) {
         LayerArgs args;
-        const uint32_t grid = plan_layer(n, k, t, remap, &args);
+        const uint32_t grid = plan_layer(n, k, t, chunk, nt, &args);
         hipEvent_t e0 = nullptr, e1 = nullptr;
         if (prof) {
             e0 = profile_event();
@@ -455,7 +462,7 @@ static int solve_int(int n, const int64_t *a, int64_t lda, perm_int_t *out, void
     HIPCALL(hipMemcpyAsync(d_a, packed.data(), packed.size() * 8, hipMemcpyHostToDevice, s), "upload matrix");
     HIPCALL(hipMemcpyAsync(d_primes, ps.data(), Rt * 8, hipMemcpyHostToDevice, s), "upload primes");
     const int t = tuned_layer_t(n);
-    const int remap = tuned_layer_remap(n);
+    const int chunk = tuned_layer_remap(n);
     const bool prof = profiling_on();
     for (int s0 = 0; s0 < Rt; s0 += rp) {
         const int cnt = std::min(rp, Rt - s0);
@@ -463,7 +470,7 @@ static int solve_int(int n, const int64_t *a, int64_t lda, perm_int_t *out, void
         uint64_t *prev = buf0, *next = buf1;
         for (int k = 2; k <= n; k++) {
             LayerArgs args;
-            const uint32_t grid = plan_layer(n, k, t, remap, &args);
+            const uint32_t grid = plan_layer(n, k, t, chunk, 0, &args);
             hipEvent_t e0 = nullptr, e1 = nullptr;
             if (prof) {
                 e0 = profile_event();
@@ -832,7 +839,10 @@ int perm_solve_batch(perm_dtype_t dt, int count, const int32_t *ns, const int64_
         if (flags & ~(PERM_BATCH_SYNC | PERM_BATCH_GRAPH | PERM_BATCH_REUSE))
             return set_error(PERM_EINVAL, "unknown flags 0x%x", flags);
         if (count == 0) return PERM_OK;
-        if (!ns || !offsets || !mats || !results || !workspace) return set_error(PERM_EINVAL, "null pointer");
+        if (!ns || !offsets || !results || !workspace) return set_error(PERM_EINVAL, "null pointer");
+        bool any_entries = false;
+        for (int i = 0; i < count; i++) any_entries |= ns[i] > 0;
+        if (!mats && any_entries) return set_error(PERM_EINVAL, "null matrix pointer");
         for (int i = 0; i < count; i++) {
             if (ns[i] < 0) return set_error(PERM_EINVAL, "ns[%d] = %d < 0", i, ns[i]);
             if (ns[i] > PERM_BATCH_N_MAX)
@@ -865,8 +875,10 @@ int perm_tuning_set(const perm_tuning_t *in) {
         const int t = in->layer_t[n];
         if (t != 0 && (t < 1 || t > kTMax || t > n || n - t > kHighBits))
             return set_error(PERM_EINVAL, "layer_t[%d] = %d impossible", n, t);
-        if (in->layer_xcd_remap[n] < -1 || in->layer_xcd_remap[n] > 1)
+        if (in->layer_xcd_remap[n] < -1 || in->layer_xcd_remap[n] > 4096)
             return set_error(PERM_EINVAL, "layer_xcd_remap[%d] = %d", n, in->layer_xcd_remap[n]);
+        if (in->layer_flags[n] & ~1)
+            return set_error(PERM_EINVAL, "layer_flags[%d] = %d", n, in->layer_flags[n]);
     }
     for (int n = 0; n <= PERM_BATCH_N_MAX; n++) {
         const int g = in->batch_group[n];
@@ -933,6 +945,7 @@ int perm_tuning_load(const char *path) {
     std::memset(&t, 0, sizeof t);
     if (!json_int_array(s, "layer_t", t.layer_t, PERM_N_MAX + 1) ||
         !json_int_array(s, "layer_xcd_remap", t.layer_xcd_remap, PERM_N_MAX + 1) ||
+        !json_int_array(s, "layer_flags", t.layer_flags, PERM_N_MAX + 1) ||
         !json_int_array(s, "batch_group", t.batch_group, PERM_BATCH_N_MAX + 1))
         return set_error(PERM_EINVAL, "malformed tuning file %s", path);
     return perm_tuning_set(&t);
@@ -955,6 +968,7 @@ int perm_tuning_save(const char *path) {
     };
     arr("layer_t", t.layer_t, PERM_N_MAX + 1, false);
     arr("layer_xcd_remap", t.layer_xcd_remap, PERM_N_MAX + 1, false);
+    arr("layer_flags", t.layer_flags, PERM_N_MAX + 1, false);
     arr("batch_group", t.batch_group, PERM_BATCH_N_MAX + 1, true);
     std::fprintf(f, "}\n");
     std::fclose(f);

@@ -23,6 +23,7 @@ int prepare_device(hipStream_t s, int *device);
 // Tuning lookups (process-wide table, defaults when unset).
 int tuned_layer_t(int n);
 int tuned_layer_remap(int n);
+int tuned_layer_flags(int n);
 int tuned_batch_group(int n, size_t lds_bytes, int elem_bytes);
 
 // Complex solve of a device matrix into a device result, stream-ordered.

@@ -76,7 +76,8 @@ constexpr uint32_t highlist_off(int m) {
 struct LayerArgs {
     int n, k, t;
     int ngroups;
-    int remap;                // XCD-aware tile order
+    int chunk;                // XCD chunking of the tile order (0 = hardware order)
+    int nt_store;             // non-temporal stores of the outputs
     uint32_t lds_window;      // entries reserved for the largest low window
     int32_t kp[kMaxGroups];   // k' of group g
     uint32_t start[kMaxGroups + 1];  // first tile of group g (prefix sums)
@@ -87,7 +88,7 @@ struct LayerArgs {
 
 // Fills LayerArgs for layer k of order n with low window t; returns the
 // number of tiles (grid size).
-uint32_t plan_layer(int n, int k, int t, int remap, LayerArgs *a);
+uint32_t plan_layer(int n, int k, int t, int chunk, int nt_store, LayerArgs *a);
 
 // Dynamic LDS bytes of a layer launch.
 size_t layer_lds_bytes_c128(const LayerArgs &a);

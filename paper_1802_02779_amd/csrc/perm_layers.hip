@@ -86,12 +86,13 @@ hipError_t ensure_tables(int device, hipStream_t s) {
 }
 
 // -------------------------------------------------------------- planning
-uint32_t plan_layer(int n, int k, int t, int remap, LayerArgs *a) {
+uint32_t plan_layer(int n, int k, int t, int chunk, int nt_store, LayerArgs *a) {
     const int nh = n - t;
     a->n = n;
     a->k = k;
     a->t = t;
-    a->remap = remap;
+    a->chunk = chunk;
+    a->nt_store = nt_store;
     a->ngroups = 0;
     a->lds_window = 0;
     uint32_t tiles = 0;
@@ -120,12 +121,17 @@ size_t layer_lds_bytes_modp(const LayerArgs &a, int rp) {
     return (size_t)rp * (a.lds_window + a.t + 32) * 8 + 32 * 4;
 }
 
-// XCD-aware order: workgroup b runs on XCD b % 8; give each XCD a contiguous
-// run of tiles so neighbouring tiles (which share high windows) meet in the
-// same L2.  A bijection on [0, G).
-__device__ __forceinline__ uint32_t xcd_remap(uint32_t b, uint32_t G) {
-    const uint32_t x = b & 7u, s = b >> 3, q = G >> 3, r = G & 7u;
-    return x * q + (x < r ? x : r) + s;
+// XCD-aware order.  Workgroup b is dispatched to XCD b % 8 as that XCD's
+// (b / 8)-th workgroup.  With chunk C > 0, each XCD takes runs of C
+// consecutive tiles (tiles that share high windows then meet in one L2)
+// while the eight XCDs stay on neighbouring runs (the chip-wide working set
+// stays small).  Tiles past the last full round of 8*C keep their order.
+// A bijection on [0, G).
+__device__ __forceinline__ uint32_t xcd_chunk_remap(uint32_t b, uint32_t G, uint32_t C) {
+    const uint32_t round = 8u * C;
+    if (C == 0 || b >= (G / round) * round) return b;
+    const uint32_t x = b & 7u, s = b >> 3;
+    return ((s / C) * 8u + x) * C + (s % C);
 }
 
 struct TileInfo {
@@ -135,8 +141,7 @@ struct TileInfo {
 
 __device__ __forceinline__ TileInfo decode_tile(const LayerArgs &A) {
     TileInfo ti;
-    uint32_t tile = blockIdx.x;
-    if (A.remap) tile = xcd_remap(tile, gridDim.x);
+    const uint32_t tile = xcd_chunk_remap(blockIdx.x, gridDim.x, (uint32_t)A.chunk);
     int g = 0;
     while (g + 1 < A.ngroups && A.start[g + 1] <= tile) g++;
     ti.g = g;
@@ -254,7 +259,12 @@ __global__ __launch_bounds__(kLayerBlock) void k_layer_c128(const double2 *__res
             for (int u = 0; u < 4; u++) cfma(re, im, s_ha[q + u], w[u]);
         }
         for (; q < ti.m; q++) cfma(re, im, s_ha[q], prev[s_hb[q] + r]);
-        out[r] = make_double2(re, im);
+        if (args.nt_store) {
+            __builtin_nontemporal_store(re, &out[r].x);
+            __builtin_nontemporal_store(im, &out[r].y);
+        } else {
+            out[r] = make_double2(re, im);
+        }
     }
 }
 

@@ -168,10 +168,11 @@ def test_determinism_and_tuning_variants(P):
     saved = P.perm_tuning_get()
     try:
         for t in range(3, 16):
-            for remap in (0, 1):
+            for remap in (0, 1, 3, 16, 64):
                 tu = P.perm_tuning_t.from_buffer_copy(saved)
                 tu.layer_t[n] = t
                 tu.layer_xcd_remap[n] = remap
+                tu.layer_flags[n] = remap & 1
                 P.perm_tuning_set(tu)
                 assert c_bits(P.perm_solve(A)) == ref, (t, remap)
     finally:
