@@ -89,6 +89,10 @@ def main():
     torch.cuda.set_device(0)
     perm.lib()
     C128 = perm.PERM_COMPLEX128
+    tuning_file = os.path.join(ROOT, "paper_1802_02779_amd", "tuning", "gfx950.json")
+    tuning = "library defaults"
+    if os.path.exists(tuning_file) and perm.perm_tuning_load(tuning_file) == 0:
+        tuning = os.path.relpath(tuning_file, ROOT)
     if args.copy_calibration:
         src = torch.empty(1 << 30, dtype=torch.uint8, device="cuda")
         dst = torch.empty_like(src)
@@ -158,7 +162,7 @@ def main():
         "data": "synthetic",
         "config": {"workload": "one 28x28 complex128 permanent per step, entries iid complex Gaussian "
                                "(parts N(0,1/2)), seed 0, device-resident input",
-                   "n": n, "global_batch": 1, "parallelism": "single GPU"},
+                   "n": n, "global_batch": 1, "parallelism": "single GPU", "tuning": tuning},
         "verified_bitwise_vs_oracle": verified,
         "roofline": roofline,
     }
@@ -280,7 +284,102 @@ def extras(perm, inputs, golden, np, torch, log):
                          "launch": "graph replay of one persistent kernel"}
     log(f"batch 2^20: {med * 1000:.2f} ms ({count / med:.3e} perms/s); plain {plain_rate:.0f} perms/s")
     del d_mats, d_out, wsb
+    out["serving"] = serving(perm, inputs, np, torch, log)
     return out
+
+
+def _percentiles(lat):
+    import numpy as np
+    lat = np.sort(np.asarray(lat))
+    if lat.size == 0:
+        return {}
+    q = lambda p: float(lat[min(lat.size - 1, int(np.ceil(p * lat.size)) - 1)]) * 1000.0  # noqa: E731
+    return {"p50_ms": round(q(0.50), 3), "p99_ms": round(q(0.99), 3), "p999_ms": round(q(0.999), 3),
+            "mean_ms": round(float(lat.mean()) * 1000.0, 3)}
+
+
+def _serve_trace(perm, srv, trace, log):
+    """Submit at the trace's arrival times; returns per-request (n, latency s)."""
+    t0 = time.perf_counter()
+    tickets = []
+    for i in range(len(trace.ns)):
+        while time.perf_counter() - t0 < trace.t_arrive[i]:
+            pass
+        while True:
+            try:
+                tickets.append((perm.perm_server_submit(srv, trace.mats[i]), int(trace.ns[i])))
+                break
+            except perm.PermError as e:
+                if e.code != perm.PERM_EAGAIN:
+                    raise
+    out = []
+    for t, n in tickets:
+        while True:
+            r = perm.perm_server_poll(srv, t)
+            if r is not None:
+                st = r[1]
+                out.append((n, st.t_done - st.t_submit, st.t_submit, st.t_done))
+                break
+    return out
+
+
+def serving(perm, inputs, np, torch, log):
+    """Poisson arrivals of submatrix permanents of a 64x64 Haar unitary,
+    n uniform in 5..12 with probability 0.8, else uniform in 20..28."""
+    U = inputs.haar_unitary(64, seed=4242)
+    pool = perm.device_buffer(48 << 30)
+    res = {}
+    # saturation: a burst of requests with the trace's size mix
+    burst = inputs.poisson_trace(U, 2000, 1e9, seed=7)
+    srv = perm.perm_server_create(pool, max_large_slots=3, queue_capacity=100000, small_n_max=12,
+                                  max_small_batch=4096)
+    try:
+        t0 = time.perf_counter()
+        done = _serve_trace(perm, srv, burst, log)
+        sat = len(done) / (max(d[3] for d in done) - min(d[2] for d in done))
+        log(f"serving saturation: {sat:.0f} requests/s ({time.perf_counter() - t0:.1f}s burst)")
+        res["saturation_perms_per_s"] = round(sat, 1)
+        for frac in (0.5, 0.8):
+            rate = frac * sat
+            trace = inputs.poisson_trace(U, 6000, rate, seed=11)
+            done = _serve_trace(perm, srv, trace, log)
+            lat = [d[1] for d in done]
+            span = max(d[3] for d in done) - min(d[2] for d in done)
+            entry = {"offered_per_s": round(rate, 1), "perms_per_s": round(len(done) / span, 1)}
+            entry.update(_percentiles(lat))
+            entry["small_n"] = _percentiles([d[1] for d in done if d[0] <= 12])
+            entry["large_n"] = _percentiles([d[1] for d in done if d[0] > 12])
+            res[f"load_{frac}"] = entry
+            log(f"serving at {rate:.0f}/s: p50 {entry['p50_ms']} ms p99 {entry['p99_ms']} ms")
+    finally:
+        perm.perm_server_destroy(srv)
+    # the same 0.8-load trace with an 8 GiB budget (admission binds: n=28 charges 4 GiB)
+    srv = perm.perm_server_create(pool, budget_bytes=8 << 30, max_large_slots=3, queue_capacity=100000,
+                                  small_n_max=12, max_small_batch=4096)
+    try:
+        trace = inputs.poisson_trace(U, 6000, 0.8 * sat, seed=11)
+        done = _serve_trace(perm, srv, trace, log)
+        entry = {"budget_bytes": 8 << 30}
+        entry.update(_percentiles([d[1] for d in done]))
+        res["load_0.8_budget_8GiB"] = entry
+    finally:
+        perm.perm_server_destroy(srv)
+    # plain: the same trace served first-in first-out by perm_solve, one at a time
+    trace = inputs.poisson_trace(U, 6000, 0.8 * sat, seed=11)
+    ws = perm.device_buffer(perm.perm_workspace_bytes(perm.PERM_COMPLEX128, 28))
+    lat = []
+    t0 = time.perf_counter()
+    for i in range(len(trace.ns)):
+        while time.perf_counter() - t0 < trace.t_arrive[i]:
+            pass
+        perm.perm_solve(trace.mats[i], workspace=ws)
+        lat.append(time.perf_counter() - t0 - trace.t_arrive[i])
+    span = time.perf_counter() - t0
+    plain = {"perms_per_s": round(len(lat) / span, 1)}
+    plain.update(_percentiles(lat))
+    res["plain_fifo_perm_solve_load_0.8"] = plain
+    log(f"plain FIFO: p50 {plain['p50_ms']} ms p99 {plain['p99_ms']} ms")
+    return res
 
 
 def cpu_baseline(inputs, log):

@@ -1,0 +1,142 @@
+"""Autotuner for libpermgpu's tile and schedule parameters.
+
+    python -m paper_1802_02779_amd.autotune [--out FILE] [--layer-n 20,24,26,28,30] [--batch]
+
+For each order n it times the candidates of one path on seeded synthetic
+inputs through the C ABI and keeps the fastest candidate whose result is
+bitwise equal to the result of the library's default configuration (every
+parameter here only changes the schedule, so any difference would be a bug and
+disqualifies the candidate):
+
+* layer sweep (perm_solve_async, complex128): low-window width t, XCD chunk
+  of the tile order, non-temporal output stores;
+* batched kernel (perm_solve_batch, complex128): threads per matrix.
+
+The winners go into the process-wide tuning table (perm_tuning_set) and are
+written with perm_tuning_save, a JSON file keyed by GPU architecture, CU count
+and HIP runtime version; perm_tuning_load ignores a file written for another
+key.  All timing runs in the library's kernels; this module only drives them.
+"""
+from __future__ import annotations
+
+import argparse
+import os
+import sys
+import time
+
+import numpy as np
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+DEFAULT_FILE = os.path.join(HERE, "tuning", "gfx950.json")
+
+
+def _time_ms(fn, reps: int, sync) -> float:
+    fn()
+    sync()
+    ts = []
+    for _ in range(reps):
+        t0 = time.perf_counter()
+        fn()
+        sync()
+        ts.append((time.perf_counter() - t0) * 1000.0)
+    return float(np.median(ts))
+
+
+def tune_layer(perm, inputs, torch, n: int, log=print, reps: int = 3):
+    C = perm.PERM_COMPLEX128
+    A = inputs.complex_gaussian(n, seed=n)
+    d_a = torch.from_numpy(A).cuda()
+    d_r = torch.zeros(1, dtype=torch.complex128, device="cuda")
+    ws = perm.device_buffer(perm.perm_workspace_bytes(C, n))
+    base = perm.perm_tuning_get()
+    default = perm.perm_tuning_t.from_buffer_copy(base)
+    default.layer_t[n] = 0
+    default.layer_xcd_remap[n] = -1
+    default.layer_flags[n] = 0
+    perm.perm_tuning_set(default)
+    run = lambda: perm.perm_solve_async(n, d_a, n, d_r, ws)  # noqa: E731
+    ref_ms = _time_ms(run, reps, torch.cuda.synchronize)
+    ref = d_r.cpu().numpy().view(np.uint64).copy()
+    best = (ref_ms, 0, -1, 0)
+    t_lo, t_hi = max(1, n - 17, n - 19), min(15, n)
+    for t in range(max(t_lo, 8), t_hi + 1):
+        for chunk in (0, 16, 64, 256):
+            for nt in (0, 1):
+                cand = perm.perm_tuning_t.from_buffer_copy(default)
+                cand.layer_t[n] = t
+                cand.layer_xcd_remap[n] = chunk
+                cand.layer_flags[n] = nt
+                perm.perm_tuning_set(cand)
+                ms = _time_ms(run, reps, torch.cuda.synchronize)
+                same = (d_r.cpu().numpy().view(np.uint64) == ref).all()
+                if not same:
+                    log(f"  n={n} t={t} chunk={chunk} nt={nt}: result differs, rejected")
+                    continue
+                if ms < best[0]:
+                    best = (ms, t, chunk, nt)
+    final = perm.perm_tuning_t.from_buffer_copy(base)
+    final.layer_t[n], final.layer_xcd_remap[n], final.layer_flags[n] = best[1], best[2], best[3]
+    perm.perm_tuning_set(final)
+    log(f"layer n={n}: default {ref_ms:.3f} ms -> t={best[1]} chunk={best[2]} nt={best[3]} {best[0]:.3f} ms")
+    return best
+
+
+def tune_batch(perm, inputs, torch, n: int, count: int = 1 << 15, log=print, reps: int = 5):
+    C = perm.PERM_COMPLEX128
+    U = inputs.haar_unitary(64, seed=2018)
+    b = inputs.submatrix_batch(U, count, n, n, seed=n)
+    d_mats = torch.from_numpy(b.mats).cuda()
+    d_out = torch.zeros(count, dtype=torch.complex128, device="cuda")
+    ws = perm.device_buffer(perm.perm_batch_workspace_bytes(C, b.ns))
+    base = perm.perm_tuning_get()
+    cand = perm.perm_tuning_t.from_buffer_copy(base)
+    cand.batch_group[n] = 0
+    perm.perm_tuning_set(cand)
+    run = lambda: perm.perm_solve_batch(C, b.ns, b.offsets, d_mats, d_out, ws)  # noqa: E731
+    ref_ms = _time_ms(run, reps, torch.cuda.synchronize)
+    ref = d_out.cpu().numpy().view(np.uint64).copy()
+    best = (ref_ms, 0)
+    for g in (16, 32, 64, 128, 256):
+        cand = perm.perm_tuning_t.from_buffer_copy(base)
+        cand.batch_group[n] = g
+        perm.perm_tuning_set(cand)
+        ms = _time_ms(run, reps, torch.cuda.synchronize)
+        if not (d_out.cpu().numpy().view(np.uint64) == ref).all():
+            log(f"  batch n={n} group={g}: result differs, rejected")
+            continue
+        if ms < best[0]:
+            best = (ms, g)
+    final = perm.perm_tuning_t.from_buffer_copy(base)
+    final.batch_group[n] = best[1]
+    perm.perm_tuning_set(final)
+    log(f"batch n={n}: default {ref_ms:.3f} ms -> group={best[1]} {best[0]:.3f} ms "
+        f"({count / best[0] * 1e3:.3e} perms/s)")
+    return best
+
+
+def main(argv=None):
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--out", default=DEFAULT_FILE)
+    ap.add_argument("--layer-n", default="16,20,24,26,28,30")
+    ap.add_argument("--batch", action="store_true")
+    args = ap.parse_args(argv)
+    sys.path.insert(0, os.path.dirname(HERE))
+    import torch
+
+    from paper_1802_02779_amd import inputs, perm
+    torch.cuda.set_device(0)
+    perm.lib()
+    if os.path.exists(args.out):
+        perm.perm_tuning_load(args.out)
+    for n in [int(x) for x in args.layer_n.split(",") if x]:
+        tune_layer(perm, inputs, torch, n)
+    if args.batch:
+        for n in range(3, 13):
+            tune_batch(perm, inputs, torch, n)
+    os.makedirs(os.path.dirname(args.out), exist_ok=True)
+    perm.perm_tuning_save(args.out)
+    print(f"key {perm.perm_tuning_key()} -> {args.out}")
+
+
+if __name__ == "__main__":
+    main()

@@ -131,3 +131,21 @@ def test_perm_int_t_decoding(perm):
     v.limb[0] = 5
     v.limb[1] = 3
     assert v.value() == -(3 * 2 ** 64 + 5)
+
+
+def test_server_config_validation(perm):
+    L = perm.lib()
+    h = ctypes.c_void_p()
+    cfg = perm.perm_server_config_t(None, 0, 0, 1, 1, 12, 1)
+    assert L.perm_server_create(ctypes.byref(cfg), ctypes.byref(h)) == perm.PERM_EINVAL
+    buf = (ctypes.c_char * 1024)()
+    for bad in (dict(max_large_slots=0), dict(queue_capacity=0), dict(small_n_max=13),
+                dict(max_small_batch=0), dict(budget_bytes=4096)):
+        kw = dict(pool=ctypes.addressof(buf), pool_bytes=1024, budget_bytes=0, max_large_slots=1,
+                  queue_capacity=4, small_n_max=12, max_small_batch=4)
+        kw.update(bad)
+        cfg = perm.perm_server_config_t(**kw)
+        assert L.perm_server_create(ctypes.byref(cfg), ctypes.byref(h)) == perm.PERM_EINVAL, bad
+    assert L.perm_server_create(None, ctypes.byref(h)) == perm.PERM_EINVAL
+    assert L.perm_server_destroy(None) == perm.PERM_EINVAL
+    assert L.perm_server_poll(None, 1, None, None) == perm.PERM_EINVAL
