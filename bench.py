@@ -17,7 +17,6 @@ trace.  Progress goes to stderr.
 from __future__ import annotations
 
 import argparse
-import hashlib
 import json
 import math
 import os
@@ -53,11 +52,8 @@ def algorithmic_flops(n: int) -> int:
 
 
 def source_hash() -> str:
-    h = hashlib.sha256()
-    for f in ("perm_layers.hip", "perm_internal.h"):
-        with open(os.path.join(ROOT, "paper_1802_02779_amd", "csrc", f), "rb") as fh:
-            h.update(fh.read())
-    return h.hexdigest()[:16]
+    from paper_1802_02779_amd.profiling import source_hash as _h
+    return _h(ROOT)
 
 
 def bits(z):

@@ -17,7 +17,7 @@ extern __constant__ BinomTable c_binom;
 extern __device__ uint32_t g_highlist[1u << kHighBits];
 
 constexpr int kBatchBlock = 256;
-constexpr size_t kBatchLdsCap = 80 * 1024;  // two workgroups per CU
+constexpr size_t kBatchLdsCap = 70 * 1024;  // with the mask list: two workgroups per CU
 
 __device__ __forceinline__ uint32_t bbinom(int i, int j) { return c_binom.v[i][j]; }
 
@@ -34,12 +34,21 @@ __device__ __forceinline__ void bcfma(double &re, double &im, const double2 a, c
     im = __builtin_fma(a.y, p.x, im);
 }
 
-size_t batch_lds_bytes(int nmax, int elem_bytes) {
+// LDS of one workgroup: the masks below 2^nmax sorted by (popcount, value)
+// as u16 (built once per workgroup), then the matrix area: 256/G matrices of
+// (2^n table entries + n*n matrix entries) each.
+__host__ __device__ size_t batch_mask_bytes(int nmax) { return (((size_t)2 << (nmax < 0 ? 0 : nmax)) + 15) & ~(size_t)15; }
+
+size_t batch_area_bytes(int nmax, int elem_bytes) {
     if (nmax < 0) nmax = 0;
     const size_t per = ((size_t)1 << nmax) + (size_t)nmax * nmax;
     size_t need = per * elem_bytes;
     if (need < kBatchLdsCap) need = kBatchLdsCap < 4 * need ? kBatchLdsCap : 4 * need;
-    return need + 64;
+    return need;
+}
+
+size_t batch_lds_bytes(int nmax, int elem_bytes) {
+    return batch_mask_bytes(nmax) + batch_area_bytes(nmax, elem_bytes) + 64;
 }
 
 int batch_blocks_per_cu(int nmax, int elem_bytes) {
@@ -57,66 +66,193 @@ hipError_t launch_batch_reset(uint32_t *counter, hipStream_t s) {
     return hipGetLastError();
 }
 
+__device__ __forceinline__ uint32_t mask_block(int nmax, int k) {
+    uint32_t s = 0;
+    for (int u = 0; u < k; u++) s += bbinom(nmax, u);
+    return s;
+}
+
+// The mask list (built on the host, see batch_mask_list) is copied into LDS
+// once per workgroup.
+__device__ void load_masks(uint16_t *s_masks, const uint16_t *__restrict__ g_masks, int nmax) {
+    for (uint32_t i = threadIdx.x; i < (1u << nmax); i += blockDim.x) s_masks[i] = g_masks[i];
+}
+
+// F(S) of an order-N matrix lives at table position (2^N - 1) - S (the
+// complement of S): the predecessor F(S \ {j}) of any j in S is then at
+// position + 2^j, a constant offset that folds into the LDS instruction.
+template <int N>
+__device__ __forceinline__ uint32_t cpos(uint32_t S) { return ((1u << N) - 1u) - S; }
+
+constexpr int cbinom(int n, int k) {
+    if (k < 0 || k > n) return 0;
+    int r = 1;
+    for (int i = 1; i <= k; i++) r = r * (n - k + i) / i;
+    return r;
+}
+
+// One chunk of matrices of order N.  Layer by layer, each lane computes whole
+// stored values F(S) with the fixed chain over columns in ascending order;
+// the column loop is unrolled and the row of A is held in registers.
+template <int N>
+__device__ __forceinline__ void batch_chunk_c128(const BatchChunk ch, int nmax, const uint16_t *s_masks, double2 *area,
+                                                 const uint32_t *__restrict__ order, double2 *__restrict__ results) {
+    const int lg = ch.group, G = 1 << lg;
+    const int gi = threadIdx.x >> lg, lane = threadIdx.x & (G - 1);
+    constexpr int PER = (1 << N) + N * N;
+    double2 *tab = area + (size_t)gi * PER;
+    double2 *mat = tab + (1 << N);
+    const bool active = gi < (int)ch.count;
+    const uint32_t mi = active ? order[ch.first + gi] : 0u;  // needed only at the end
+    if (active)
+        for (int j = lane; j < N; j += G) tab[cpos<N>(1u << j)] = mat[j];
+    __syncthreads();
+#pragma unroll
+    for (int k = 2; k <= N; k++) {
+        if (active) {
+            const uint16_t *ml = s_masks + mask_block(nmax, k);
+            double2 a[N];
+#pragma unroll
+            for (int j = 0; j < N; j++) a[j] = mat[(k - 1) * N + j];
+            const int cnt = cbinom(N, k);
+            for (int i = lane; i < cnt; i += G) {
+                const uint32_t S = ml[i];
+                const double2 *t0 = tab + cpos<N>(S);
+                // all predecessor loads first (independent), then the chain;
+                // a column outside S contributes no term
+                double2 p[N];
+#pragma unroll
+                for (int j = 0; j < N; j++)
+                    if ((S >> j) & 1u) p[j] = t0[1u << j];
+                double re = 0.0, im = 0.0;
+#pragma unroll
+                for (int j = 0; j < N; j++) {
+                    if ((S >> j) & 1u) {
+                        asm volatile("");  // keep this a masked block rather than selects
+                        bcfma(re, im, a[j], p[j]);
+                    }
+                }
+                tab[cpos<N>(S)] = make_double2(re, im);
+            }
+        }
+        __syncthreads();
+    }
+    if (active && lane == 0) results[mi] = tab[cpos<N>((1u << N) - 1)];
+    __syncthreads();
+}
+
+// Orders 0..2 (rare): trivial values, written directly.
+__device__ __forceinline__ void batch_chunk_tiny_c128(const BatchChunk ch, const double2 *__restrict__ mats,
+                                      const int64_t *__restrict__ offsets, const uint32_t *__restrict__ order,
+                                      double2 *__restrict__ results) {
+    for (uint32_t g = threadIdx.x; g < ch.count; g += blockDim.x) {
+        const uint32_t mi = order[ch.first + g];
+        const double2 *a = mats + offsets[mi];
+        double2 r;
+        if (ch.n == 0) {
+            r = make_double2(1.0, 0.0);
+        } else if (ch.n == 1) {
+            r = a[0];
+        } else {  // F({0,1}) = a[1][0] * a[0][1] + a[1][1] * a[0][0], chain over j = 0, 1
+            double re = 0.0, im = 0.0;
+            bcfma(re, im, a[2], a[1]);
+            bcfma(re, im, a[3], a[0]);
+            r = make_double2(re, im);
+        }
+        results[mi] = r;
+    }
+    __syncthreads();
+}
+
+// Entries of a chunk's matrices staged through registers: thread i holds
+// flat entries i, i + 256, ... (at most kPrefetch of them; the planner keeps
+// (256 / G) * n * n <= 256 * kPrefetch).
+constexpr int kPrefetch = 4;
+
+struct ChunkPrefetch {
+    double2 v[kPrefetch];
+};
+
+__device__ __forceinline__ void prefetch_chunk(ChunkPrefetch &R, const BatchChunk ch,
+                                               const double2 *__restrict__ mats,
+                                               const int64_t *__restrict__ offsets,
+                                               const uint32_t *__restrict__ order) {
+    const uint32_t nn = (uint32_t)ch.n * ch.n, tot = nn * ch.count;
+#pragma unroll
+    for (int r = 0; r < kPrefetch; r++) {
+        const uint32_t f = threadIdx.x + (uint32_t)r * kBatchBlock;
+        if (f < tot) {
+            const uint32_t g = f / nn, e = f - g * nn;
+            R.v[r] = mats[offsets[order[ch.first + g]] + e];
+        }
+    }
+}
+
+__device__ __forceinline__ void stage_chunk(const ChunkPrefetch &R, const BatchChunk ch, double2 *area) {
+    const uint32_t nn = (uint32_t)ch.n * ch.n, tot = nn * ch.count;
+    const uint32_t per = (1u << ch.n) + nn;
+#pragma unroll
+    for (int r = 0; r < kPrefetch; r++) {
+        const uint32_t f = threadIdx.x + (uint32_t)r * kBatchBlock;
+        if (f < tot) {
+            const uint32_t g = f / nn, e = f - g * nn;
+            area[(size_t)g * per + (1u << ch.n) + e] = R.v[r];
+        }
+    }
+}
+
 __global__ __launch_bounds__(kBatchBlock) void k_batch_c128(
     const double2 *__restrict__ mats, const int64_t *__restrict__ offsets,
     const uint32_t *__restrict__ order, const BatchChunk *__restrict__ chunks, uint32_t nchunks,
-    uint32_t *counter, double2 *__restrict__ results) {
+    uint32_t *counter, double2 *__restrict__ results, int nmax, const uint16_t *__restrict__ g_masks) {
     extern __shared__ double2 bsm[];
-    __shared__ uint32_t s_chunk;
+    __shared__ uint32_t s_next;
+    uint16_t *s_masks = (uint16_t *)bsm;
+    double2 *area = bsm + batch_mask_bytes(nmax) / sizeof(double2);
+    load_masks(s_masks, g_masks, nmax);
+    if (threadIdx.x == 0) s_next = atomicAdd(counter, 1u);
+    __syncthreads();
+    uint32_t c = s_next;
+    if (c >= nchunks) return;  // uniform: every thread read the same index
+    BatchChunk ch = chunks[c];
+    ChunkPrefetch R;
+    prefetch_chunk(R, ch, mats, offsets, order);
+    __syncthreads();  // everyone has read s_next
     for (;;) {
-        if (threadIdx.x == 0) s_chunk = atomicAdd(counter, 1u);
+        // current chunk's matrices into LDS, claim the next chunk
+        if (ch.n >= 3) stage_chunk(R, ch, area);
+        if (threadIdx.x == 0) s_next = atomicAdd(counter, 1u);
         __syncthreads();
-        const uint32_t c = s_chunk;
-        __syncthreads();
-        if (c >= nchunks) break;
-        const BatchChunk ch = chunks[c];
-        const int n = ch.n, lg = ch.group, G = 1 << lg;
-        const int gi = threadIdx.x >> lg, lane = threadIdx.x & (G - 1);
-        const int per = (1 << n) + n * n;
-        double2 *tab = bsm + (size_t)gi * per;
-        double2 *mat = tab + (1 << n);
-        const bool active = gi < (int)ch.count;
-        uint32_t mi = 0;
-        if (active) {
-            mi = order[ch.first + gi];
-            const double2 *src = mats + offsets[mi];
-            for (int i = lane; i < n * n; i += G) mat[i] = src[i];
+        const uint32_t c2 = s_next;
+        BatchChunk ch2 = ch;
+        if (c2 < nchunks) {
+            ch2 = chunks[c2];
+            prefetch_chunk(R, ch2, mats, offsets, order);  // in flight during the compute below
         }
-        __syncthreads();
-        if (active)
-            for (int j = lane; j < n; j += G) tab[1u << j] = mat[j];
-        __syncthreads();
-        for (int k = 2; k <= n; k++) {
-            if (active) {
-                const uint32_t cnt = bbinom(n, k);
-                const uint32_t *ml = g_highlist + highlist_block(k);
-                const double2 *arow = mat + (k - 1) * n;
-                for (uint32_t i = lane; i < cnt; i += G) {
-                    const uint32_t S = ml[i];
-                    double re = 0.0, im = 0.0;
-                    uint32_t b = S;
-                    while (b) {
-                        const int j = __ffs(b) - 1;
-                        b &= b - 1;
-                        bcfma(re, im, arow[j], tab[S ^ (1u << j)]);
-                    }
-                    tab[S] = make_double2(re, im);
-                }
-            }
-            __syncthreads();
+        switch (ch.n) {
+        case 12: batch_chunk_c128<12>(ch, nmax, s_masks, area, order, results); break;
+        case 11: batch_chunk_c128<11>(ch, nmax, s_masks, area, order, results); break;
+        case 10: batch_chunk_c128<10>(ch, nmax, s_masks, area, order, results); break;
+        case 9: batch_chunk_c128<9>(ch, nmax, s_masks, area, order, results); break;
+        case 8: batch_chunk_c128<8>(ch, nmax, s_masks, area, order, results); break;
+        case 7: batch_chunk_c128<7>(ch, nmax, s_masks, area, order, results); break;
+        case 6: batch_chunk_c128<6>(ch, nmax, s_masks, area, order, results); break;
+        case 5: batch_chunk_c128<5>(ch, nmax, s_masks, area, order, results); break;
+        case 4: batch_chunk_c128<4>(ch, nmax, s_masks, area, order, results); break;
+        case 3: batch_chunk_c128<3>(ch, nmax, s_masks, area, order, results); break;
+        default: batch_chunk_tiny_c128(ch, mats, offsets, order, results); break;
         }
-        if (active && lane == 0)
-            results[mi] = n == 0 ? make_double2(1.0, 0.0) : tab[(1u << n) - 1];
-        __syncthreads();
+        if (c2 >= nchunks) break;  // uniform
+        ch = ch2;
     }
 }
 
 hipError_t launch_batch_c128(const void *mats, const int64_t *offsets, const uint32_t *order,
                              const BatchChunk *chunks, uint32_t nchunks, uint32_t *counter,
-                             void *results, int nmax, int grid, hipStream_t s) {
+                             void *results, int nmax, const uint16_t *masks, int grid, hipStream_t s) {
     const size_t lds = batch_lds_bytes(nmax, 16);
     hipLaunchKernelGGL(k_batch_c128, dim3(grid), dim3(kBatchBlock), lds, s, (const double2 *)mats,
-                       offsets, order, chunks, nchunks, counter, (double2 *)results);
+                       offsets, order, chunks, nchunks, counter, (double2 *)results, nmax, masks);
     return hipGetLastError();
 }
 
@@ -138,8 +274,9 @@ __global__ __launch_bounds__(kBatchBlock) void k_batch_modp(
     const uint32_t *__restrict__ order, const BatchChunk *__restrict__ chunks, uint32_t nchunks,
     uint32_t *counter, const uint64_t *__restrict__ primes, int nprimes, uint64_t *__restrict__ res,
     uint32_t count) {
-    extern __shared__ uint64_t bsu[];
+    extern __shared__ uint64_t bsu_all[];
     __shared__ uint32_t s_chunk;
+    uint64_t *bsu = bsu_all;
     for (;;) {
         if (threadIdx.x == 0) s_chunk = atomicAdd(counter, 1u);
         __syncthreads();

@@ -315,7 +315,9 @@ int tuned_batch_group(int n, size_t lds_bytes, int elem_bytes) {
         g = defaults[n];
     }
     const size_t per = (((size_t)1 << n) + (size_t)n * n) * elem_bytes;
-    while (g < 256 && (size_t)(256 / g) * per > lds_bytes - 64) g *= 2;
+    while (g < 256 && (size_t)(256 / g) * per > lds_bytes) g *= 2;
+    // the batched kernel stages a chunk's matrices through at most 1024 entries of registers
+    while (g < 256 && (256 / g) * n * n > 1024) g *= 2;
     return g;
 }
 
@@ -494,6 +496,31 @@ static int solve_int(int n, const int64_t *a, int64_t lda, perm_int_t *out, void
 }
 
 // -------------------------------------------------------------- batch
+void batch_mask_list(int nmax, uint16_t *out) {
+    size_t pos = 0;
+    for (int k = 0; k <= nmax; k++) {
+        if (k == 0) {
+            out[pos++] = 0;
+            continue;
+        }
+        for (int h = k - 1; h < nmax; h++) {
+            // masks of popcount k with highest bit h, in increasing order, bucketed by low bits
+            std::vector<uint16_t> bucket[8];
+            for (uint32_t m = 1u << h; m < (2u << h); m++)
+                if (__builtin_popcount(m) == k) bucket[m & 7].push_back((uint16_t)m);
+            size_t idx[8] = {0, 0, 0, 0, 0, 0, 0, 0};
+            for (bool more = true; more;) {
+                more = false;
+                for (int b = 0; b < 8; b++)
+                    if (idx[b] < bucket[b].size()) {
+                        out[pos++] = bucket[b][idx[b]++];
+                        more = true;
+                    }
+            }
+        }
+    }
+}
+
 struct BatchPlan {
     std::vector<uint32_t> order;
     std::vector<BatchChunk> chunks;
@@ -528,7 +555,7 @@ static void build_batch_plan(int count, const int32_t *ns, size_t lds, int elem,
 }
 
 struct BatchLayout {
-    size_t counter, order, offsets, chunks, primes, res, mats, total;
+    size_t counter, order, offsets, chunks, masks, primes, res, mats, total;
 };
 
 static BatchLayout batch_layout(perm_dtype_t dt, int count, const int32_t *ns) {
@@ -542,6 +569,8 @@ static BatchLayout batch_layout(perm_dtype_t dt, int count, const int32_t *ns) {
     off += align256((size_t)count * 8);
     L.chunks = off;
     off += align256((size_t)count * sizeof(BatchChunk));
+    L.masks = off;
+    off += align256((size_t)2 << PERM_BATCH_N_MAX);
     if (dt == PERM_INT64) {
         size_t elems = 0;
         for (int i = 0; i < count; i++) elems += (size_t)ns[i] * ns[i];
@@ -589,7 +618,7 @@ static int batch_c128(int count, const int32_t *ns, const int64_t *offsets, cons
     if (!ge) {
         int nmax = 0;
         for (int i = 0; i < count; i++) nmax = std::max(nmax, (int)ns[i]);
-        const size_t lds = batch_lds_bytes(nmax, 16);
+        const size_t lds = batch_area_bytes(nmax, 16);
         BatchPlan bp;
         build_batch_plan(count, ns, lds, 16, bp);
         const uint32_t nchunks = (uint32_t)bp.chunks.size();
@@ -600,13 +629,25 @@ static int batch_c128(int count, const int32_t *ns, const int64_t *offsets, cons
         HIPCALL(hipMemcpyAsync(base + L.chunks, bp.chunks.data(), nchunks * sizeof(BatchChunk),
                                hipMemcpyHostToDevice, s),
                 "upload chunks");
+        {
+            static std::mutex mask_mu;
+            static std::vector<uint16_t> mask_lists[PERM_BATCH_N_MAX + 1];
+            std::lock_guard<std::mutex> mlk(mask_mu);
+            auto &ml = mask_lists[nmax];
+            if (ml.empty()) {
+                ml.resize((size_t)1 << nmax);
+                batch_mask_list(nmax, ml.data());
+            }
+            HIPCALL(hipMemcpyAsync(base + L.masks, ml.data(), ml.size() * 2, hipMemcpyHostToDevice, s),
+                    "upload masks");
+        }
         const int grid = std::max(1, std::min<int>((int)nchunks, cu_count() * batch_blocks_per_cu(nmax, 16)));
         auto enqueue = [&](hipStream_t q) -> hipError_t {
             hipError_t e = launch_batch_reset(d_counter, q);
             if (e != hipSuccess) return e;
             return launch_batch_c128(mats, (const int64_t *)(base + L.offsets), (const uint32_t *)(base + L.order),
                                      (const BatchChunk *)(base + L.chunks), nchunks, d_counter, results, nmax,
-                                     grid, q);
+                                     (const uint16_t *)(base + L.masks), grid, q);
         };
         if (!use_graph) {
             glk.unlock();
@@ -700,7 +741,7 @@ static int batch_int(int count, const int32_t *ns, const int64_t *offsets, const
         std::memcpy(&packed[dev_off[i]], mats + offsets[i], (size_t)ns[i] * ns[i] * 8);
     int nmax = 0;
     for (int i = 0; i < count; i++) nmax = std::max(nmax, (int)ns[i]);
-    const size_t lds = batch_lds_bytes(nmax, 8);
+    const size_t lds = batch_lds_bytes(nmax, 8) - 64;
     BatchPlan bp;
     build_batch_plan(count, ns, lds, 8, bp);
     const uint32_t nchunks = (uint32_t)bp.chunks.size();

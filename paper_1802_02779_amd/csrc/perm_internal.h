@@ -123,12 +123,19 @@ struct BatchChunk {
 hipError_t launch_batch_reset(uint32_t *counter, hipStream_t s);
 hipError_t launch_batch_c128(const void *mats, const int64_t *offsets, const uint32_t *order,
                              const BatchChunk *chunks, uint32_t nchunks, uint32_t *counter,
-                             void *results, int nmax, int grid, hipStream_t s);
+                             void *results, int nmax, const uint16_t *masks, int grid, hipStream_t s);
 hipError_t launch_batch_modp(const int64_t *mats, const int64_t *offsets, const uint32_t *order,
                              const BatchChunk *chunks, uint32_t nchunks, uint32_t *counter,
                              const uint64_t *primes, int nprimes, uint64_t *res, uint32_t count,
                              int nmax, int grid, hipStream_t s);
 size_t batch_lds_bytes(int nmax, int elem_bytes);
+// Masks below 2^nmax grouped by popcount; inside a popcount the masks with
+// highest bit h come after all lower ones (so the masks of popcount k below
+// 2^n are the first C(n,k) entries for every n <= nmax), and each run of one
+// highest bit is interleaved by the mask's low three bits so that eight
+// neighbouring lanes read eight different LDS bank groups.
+void batch_mask_list(int nmax, uint16_t *out);
+size_t batch_area_bytes(int nmax, int elem_bytes);
 int batch_blocks_per_cu(int nmax, int elem_bytes);
 
 }  // namespace permgpu

@@ -36,5 +36,80 @@ def main():
         print(f"\nsum of the step's layer launches: {tot / 1e6:.3f} ms")
 
 
-if __name__ == "__main__":
+if __name__ == "__main__" and not (len(sys.argv) > 1 and sys.argv[1] == "counters"):
     main()
+
+
+def source_hash(root: str) -> str:
+    """Hash of the layer-sweep sources: counter data is valid only for them."""
+    import hashlib
+    import os
+    h = hashlib.sha256()
+    for f in ("perm_layers.hip", "perm_internal.h"):
+        with open(os.path.join(root, "paper_1802_02779_amd", "csrc", f), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()[:16]
+
+
+def counters(fetch_db: str, write_db: str, cmd: str, root: str, n: int = 28, extra_dbs=()):
+    """HBM traffic of the complex layer sweep from two rocprofv3 --pmc runs
+    (FETCH_SIZE, then WRITE_SIZE), each scaled by what the same counter reads
+    for the 1 GiB device-to-device copy the run starts with.  Returns
+    (markdown, json-able dict)."""
+    import collections
+
+    def load(db):
+        cur = sqlite3.connect(db).cursor()
+        rows = list(cur.execute("select dispatch_id, kernel_name, grid_size, counter_name, value, duration "
+                                "from counters_collection order by dispatch_id"))
+        cal, lay = {}, collections.OrderedDict()
+        for d, k, g, c, v, dur in rows:
+            if "copyBuffer" in k and g == 131072:
+                cal[c] = v
+            if "k_layer_c128" in k:
+                lay.setdefault(d, {})[c] = v
+        return cal, [lay[d] for d in list(lay)[: n - 1]]
+
+    fcal, fl = load(fetch_db)
+    wcal, wl = load(write_db)
+    extra = [load(db)[1] for db in extra_dbs]
+    ff = 1048576.0 / fcal["FETCH_SIZE"]
+    wf = 1048576.0 / wcal["WRITE_SIZE"]
+    lines = [f"commands:\n\n    {cmd}\n",
+             f"calibration (1 GiB device copy): FETCH_SIZE reads {fcal['FETCH_SIZE']:.0f} KiB "
+             f"(factor {ff:.4f}), WRITE_SIZE reads {wcal['WRITE_SIZE']:.0f} KiB (factor {wf:.4f})\n",
+             "| layer k | algorithmic read MB | fetched MB | algorithmic write MB | written MB |"
+             + (" L2 hit |" if extra else ""),
+             "|---|---|---|---|---|" + ("---|" if extra else "")]
+    tf = tw = ta = 0.0
+    hits = misses = 0.0
+    for i, k in enumerate(range(2, n + 1)):
+        ar, aw = 16 * math.comb(n, k - 1), 16 * math.comb(n, k)
+        f = fl[i]["FETCH_SIZE"] * 1024 * ff
+        w = wl[i]["WRITE_SIZE"] * 1024 * wf
+        tf, tw, ta = tf + f, tw + w, ta + ar + aw
+        row = f"| {k} | {ar / 1e6:.1f} | {f / 1e6:.1f} | {aw / 1e6:.1f} | {w / 1e6:.1f} |"
+        if extra and "TCC_HIT_sum" in extra[0][i]:
+            h, m = extra[0][i]["TCC_HIT_sum"], extra[0][i]["TCC_MISS_sum"]
+            hits, misses = hits + h, misses + m
+            row += f" {h / max(h + m, 1):.3f} |"
+        lines.append(row)
+    lines.append(f"\nper step: fetched {tf / 1e9:.2f} GB, written {tw / 1e9:.2f} GB, algorithmic "
+                 f"{ta / 1e9:.2f} GB, amplification {(tf + tw) / ta:.2f}"
+                 + (f", L2 hit rate {hits / (hits + misses):.3f}" if hits + misses else ""))
+    data = {"source_hash": source_hash(root), "n": n, "launches": n - 1,
+            "hbm_bytes_per_launch": int((tf + tw) / (n - 1)), "fetch_bytes_per_step": int(tf),
+            "write_bytes_per_step": int(tw), "algorithmic_bytes_per_step": int(ta),
+            "fetch_factor": ff, "write_factor": wf}
+    return "\n".join(lines) + "\n", data
+
+
+if __name__ == "__main__" and len(sys.argv) > 1 and sys.argv[1] == "counters":
+    import json
+    import os
+    root = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+    md, data = counters(sys.argv[2], sys.argv[3], sys.argv[4], root,
+                        extra_dbs=sys.argv[5:])
+    print(md)
+    with open(os.path.join(root, "profiles", "layer_c128_n28_counters.json"), "w") as f:
+        json.dump(data, f, indent=1)
