@@ -466,6 +466,12 @@ static int solve_int(int n, const int64_t *a, int64_t lda, perm_int_t *out, void
     const int t = tuned_layer_t(n);
     const int chunk = tuned_layer_remap(n);
     const bool prof = profiling_on();
+    std::vector<int> binary(n, 1);
+    for (int i = 0; i < n; i++)
+        for (int j = 0; j < n; j++) {
+            const int64_t v = packed[(size_t)i * n + j];
+            if (v != 0 && v != 1) binary[i] = 0;
+        }
     for (int s0 = 0; s0 < Rt; s0 += rp) {
         const int cnt = std::min(rp, Rt - s0);
         HIPCALL(launch_reduce_modp(d_a, n, d_primes + s0, cnt, d_red, buf0, plane, s), "reduce kernel");
@@ -473,6 +479,7 @@ static int solve_int(int n, const int64_t *a, int64_t lda, perm_int_t *out, void
         for (int k = 2; k <= n; k++) {
             LayerArgs args;
             const uint32_t grid = plan_layer(n, k, t, chunk, 0, &args);
+            args.binary_row = binary[k - 1];
             hipEvent_t e0 = nullptr, e1 = nullptr;
             if (prof) {
                 e0 = profile_event();

@@ -78,6 +78,7 @@ struct LayerArgs {
     int ngroups;
     int chunk;                // XCD chunking of the tile order (0 = hardware order)
     int nt_store;             // non-temporal stores of the outputs
+    int binary_row;           // integer path: this layer's row of A is all 0/1
     uint32_t lds_window;      // entries reserved for the largest low window
     int32_t kp[kMaxGroups];   // k' of group g
     uint32_t start[kMaxGroups + 1];  // first tile of group g (prefix sums)

@@ -93,6 +93,7 @@ uint32_t plan_layer(int n, int k, int t, int chunk, int nt_store, LayerArgs *a) 
     a->t = t;
     a->chunk = chunk;
     a->nt_store = nt_store;
+    a->binary_row = 0;
     a->ngroups = 0;
     a->lds_window = 0;
     uint32_t tiles = 0;
@@ -324,7 +325,9 @@ hipError_t launch_reduce_modp(const int64_t *a_dev, int n, const uint64_t *prime
     return hipGetLastError();
 }
 
-template <int RP>
+// BIN: every entry of this layer's row of A is 0 or 1 (then equal in every
+// residue), so a term is either skipped or a plain addition.
+template <int RP, bool BIN>
 __global__ __launch_bounds__(kLayerBlock) void k_layer_modp(const uint64_t *__restrict__ prev,
                                                             uint64_t *__restrict__ next, size_t plane,
                                                             const uint64_t *__restrict__ red,
@@ -372,15 +375,32 @@ __global__ __launch_bounds__(kLayerBlock) void k_layer_modp(const uint64_t *__re
         for (int p = 0; p < ti.kp; p++) {
             const uint32_t e = lt[(uint32_t)p * ck + rr];
             const uint32_t idx = e & 0xffffu, col = e >> 16;
+            if (BIN) {
+                if (s_arow[col] != 0) {
 #pragma unroll
-            for (int r = 0; r < RP; r++) acc[r] += (u128)s_arow[r * t + col] * s_win[r * W + idx];
+                    for (int r = 0; r < RP; r++) acc[r] += s_win[r * W + idx];
+                }
+            } else {
+#pragma unroll
+                for (int r = 0; r < RP; r++) {
+                    const uint64_t a = s_arow[r * t + col];
+                    if (a != 0) acc[r] += (u128)a * s_win[r * W + idx];
+                }
+            }
         }
         for (int q = 0; q < ti.m; q++) {
             const uint32_t base = s_hb[q] + rr;
+            if (BIN) {
+                if (s_ha[q] != 0) {
 #pragma unroll
-            for (int r = 0; r < RP; r++) {
-                const uint64_t a = s_ha[r * 32 + q];
-                if (a != 0) acc[r] += (u128)a * prev[(size_t)r * plane + base];
+                    for (int r = 0; r < RP; r++) acc[r] += prev[(size_t)r * plane + base];
+                }
+            } else {
+#pragma unroll
+                for (int r = 0; r < RP; r++) {
+                    const uint64_t a = s_ha[r * 32 + q];
+                    if (a != 0) acc[r] += (u128)a * prev[(size_t)r * plane + base];
+                }
             }
         }
 #pragma unroll
@@ -388,26 +408,33 @@ __global__ __launch_bounds__(kLayerBlock) void k_layer_modp(const uint64_t *__re
     }
 }
 
-hipError_t launch_layer_modp(const uint64_t *prev, uint64_t *next, size_t plane, const uint64_t *red,
-                             const uint64_t *primes, int rp, const LayerArgs &a, uint32_t grid,
-                             hipStream_t s) {
-    const size_t lds = layer_lds_bytes_modp(a, rp);
+template <bool BIN>
+static void launch_modp_t(const uint64_t *prev, uint64_t *next, size_t plane, const uint64_t *red,
+                          const uint64_t *primes, int rp, const LayerArgs &a, uint32_t grid, size_t lds,
+                          hipStream_t s) {
     switch (rp) {
     case 1:
-        hipLaunchKernelGGL(k_layer_modp<1>, dim3(grid), dim3(kLayerBlock), lds, s, prev, next, plane,
+        hipLaunchKernelGGL((k_layer_modp<1, BIN>), dim3(grid), dim3(kLayerBlock), lds, s, prev, next, plane,
                            red, primes, a);
         break;
     case 2:
-        hipLaunchKernelGGL(k_layer_modp<2>, dim3(grid), dim3(kLayerBlock), lds, s, prev, next, plane,
-                           red, primes, a);
-        break;
-    case 3:
-        hipLaunchKernelGGL(k_layer_modp<3>, dim3(grid), dim3(kLayerBlock), lds, s, prev, next, plane,
+        hipLaunchKernelGGL((k_layer_modp<2, BIN>), dim3(grid), dim3(kLayerBlock), lds, s, prev, next, plane,
                            red, primes, a);
         break;
     default:
-        return hipErrorInvalidValue;
+        hipLaunchKernelGGL((k_layer_modp<3, BIN>), dim3(grid), dim3(kLayerBlock), lds, s, prev, next, plane,
+                           red, primes, a);
+        break;
     }
+}
+
+hipError_t launch_layer_modp(const uint64_t *prev, uint64_t *next, size_t plane, const uint64_t *red,
+                             const uint64_t *primes, int rp, const LayerArgs &a, uint32_t grid,
+                             hipStream_t s) {
+    if (rp < 1 || rp > kRPMax) return hipErrorInvalidValue;
+    const size_t lds = layer_lds_bytes_modp(a, rp);
+    if (a.binary_row) launch_modp_t<true>(prev, next, plane, red, primes, rp, a, grid, lds, s);
+    else launch_modp_t<false>(prev, next, plane, red, primes, rp, a, grid, lds, s);
     return hipGetLastError();
 }
 
