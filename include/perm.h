@@ -203,7 +203,7 @@ int perm_server_destroy(perm_server_t *s);
  *                      consecutive tiles; 0 = hardware order, -1 = default.
  *   layer_flags[n]     bit 0: non-temporal stores of layer outputs.
  *   batch_group[n]     threads that share one matrix in the batched kernel
- *                      (power of two, 16..256); 0 = library default. */
+ *                      (power of two, 16..512); 0 = library default. */
 typedef struct {
     int layer_t[PERM_N_MAX + 1];
     int layer_xcd_remap[PERM_N_MAX + 1];

@@ -96,7 +96,7 @@ def tune_batch(perm, inputs, torch, n: int, count: int = 1 << 15, log=print, rep
     ref_ms = _time_ms(run, reps, torch.cuda.synchronize)
     ref = d_out.cpu().numpy().view(np.uint64).copy()
     best = (ref_ms, 0)
-    for g in (16, 32, 64, 128, 256):
+    for g in (16, 32, 64, 128, 256, 512):
         cand = perm.perm_tuning_t.from_buffer_copy(base)
         cand.batch_group[n] = g
         perm.perm_tuning_set(cand)

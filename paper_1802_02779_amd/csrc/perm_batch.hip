@@ -15,8 +15,11 @@ namespace permgpu {
 
 extern __constant__ BinomTable c_binom;
 extern __device__ uint32_t g_highlist[1u << kHighBits];
+// Masks below 2^12 in batch order (see batch_mask_list), filled once per device.
+__device__ uint16_t g_batch_masks[1u << kBatchNMax];
 
-constexpr int kBatchBlock = 256;
+constexpr int kBatchBlock = 256;   // integer batched kernel
+constexpr int kBatchBlockC = kBatchBlockComplex;  // complex batched kernel
 constexpr size_t kBatchLdsCap = 70 * 1024;  // with the mask list: two workgroups per CU
 
 __device__ __forceinline__ uint32_t bbinom(int i, int j) { return c_binom.v[i][j]; }
@@ -35,9 +38,9 @@ __device__ __forceinline__ void bcfma(double &re, double &im, const double2 a, c
 }
 
 // LDS of one workgroup: the masks below 2^nmax sorted by (popcount, value)
-// as u16 (built once per workgroup), then the matrix area: 256/G matrices of
+// as u16 (copied once per workgroup), then the matrix area: B/G matrices of
 // (2^n table entries + n*n matrix entries) each.
-__host__ __device__ size_t batch_mask_bytes(int nmax) { return (((size_t)2 << (nmax < 0 ? 0 : nmax)) + 15) & ~(size_t)15; }
+__host__ __device__ size_t batch_mask_bytes(int) { return ((size_t)2 << kBatchNMax) + 16; }
 
 size_t batch_area_bytes(int nmax, int elem_bytes) {
     if (nmax < 0) nmax = 0;
@@ -74,8 +77,8 @@ __device__ __forceinline__ uint32_t mask_block(int nmax, int k) {
 
 // The mask list (built on the host, see batch_mask_list) is copied into LDS
 // once per workgroup.
-__device__ void load_masks(uint16_t *s_masks, const uint16_t *__restrict__ g_masks, int nmax) {
-    for (uint32_t i = threadIdx.x; i < (1u << nmax); i += blockDim.x) s_masks[i] = g_masks[i];
+__device__ void load_masks(uint16_t *s_masks) {
+    for (uint32_t i = threadIdx.x; i < (1u << kBatchNMax); i += blockDim.x) s_masks[i] = g_batch_masks[i];
 }
 
 // F(S) of an order-N matrix lives at table position (2^N - 1) - S (the
@@ -103,14 +106,14 @@ __device__ __forceinline__ void batch_chunk_c128(const BatchChunk ch, int nmax, 
     double2 *tab = area + (size_t)gi * PER;
     double2 *mat = tab + (1 << N);
     const bool active = gi < (int)ch.count;
-    const uint32_t mi = active ? order[ch.first + gi] : 0u;  // needed only at the end
+    const uint32_t mi = active ? (order ? order[ch.first + gi] : ch.first + gi) : 0u;  // used at the end
     if (active)
         for (int j = lane; j < N; j += G) tab[cpos<N>(1u << j)] = mat[j];
     __syncthreads();
 #pragma unroll
     for (int k = 2; k <= N; k++) {
         if (active) {
-            const uint16_t *ml = s_masks + mask_block(nmax, k);
+            const uint16_t *ml = s_masks + mask_block(kBatchNMax, k);
             double2 a[N];
 #pragma unroll
             for (int j = 0; j < N; j++) a[j] = mat[(k - 1) * N + j];
@@ -146,8 +149,8 @@ __device__ __forceinline__ void batch_chunk_tiny_c128(const BatchChunk ch, const
                                       const int64_t *__restrict__ offsets, const uint32_t *__restrict__ order,
                                       double2 *__restrict__ results) {
     for (uint32_t g = threadIdx.x; g < ch.count; g += blockDim.x) {
-        const uint32_t mi = order[ch.first + g];
-        const double2 *a = mats + offsets[mi];
+        const uint32_t mi = order ? order[ch.first + g] : ch.first + g;
+        const double2 *a = mats + (offsets ? offsets[mi] : 0);
         double2 r;
         if (ch.n == 0) {
             r = make_double2(1.0, 0.0);
@@ -166,7 +169,7 @@ __device__ __forceinline__ void batch_chunk_tiny_c128(const BatchChunk ch, const
 
 // Entries of a chunk's matrices staged through registers: thread i holds
 // flat entries i, i + 256, ... (at most kPrefetch of them; the planner keeps
-// (256 / G) * n * n <= 256 * kPrefetch).
+// (B / G) * n * n <= B * kPrefetch for the workgroup size B).
 constexpr int kPrefetch = 4;
 
 struct ChunkPrefetch {
@@ -180,10 +183,11 @@ __device__ __forceinline__ void prefetch_chunk(ChunkPrefetch &R, const BatchChun
     const uint32_t nn = (uint32_t)ch.n * ch.n, tot = nn * ch.count;
 #pragma unroll
     for (int r = 0; r < kPrefetch; r++) {
-        const uint32_t f = threadIdx.x + (uint32_t)r * kBatchBlock;
+        const uint32_t f = threadIdx.x + (uint32_t)r * kBatchBlockC;
         if (f < tot) {
             const uint32_t g = f / nn, e = f - g * nn;
-            R.v[r] = mats[offsets[order[ch.first + g]] + e];
+            const uint32_t mi = order ? order[ch.first + g] : ch.first + g;
+            R.v[r] = mats[(offsets ? offsets[mi] : 0) + e];
         }
     }
 }
@@ -193,7 +197,7 @@ __device__ __forceinline__ void stage_chunk(const ChunkPrefetch &R, const BatchC
     const uint32_t per = (1u << ch.n) + nn;
 #pragma unroll
     for (int r = 0; r < kPrefetch; r++) {
-        const uint32_t f = threadIdx.x + (uint32_t)r * kBatchBlock;
+        const uint32_t f = threadIdx.x + (uint32_t)r * kBatchBlockC;
         if (f < tot) {
             const uint32_t g = f / nn, e = f - g * nn;
             area[(size_t)g * per + (1u << ch.n) + e] = R.v[r];
@@ -201,31 +205,36 @@ __device__ __forceinline__ void stage_chunk(const ChunkPrefetch &R, const BatchC
     }
 }
 
-__global__ __launch_bounds__(kBatchBlock) void k_batch_c128(
+// With single.count == 1 the launch solves that one chunk (matrix 0 at
+// offset 0, no work list, no counter); otherwise it runs the persistent loop.
+// At most 128 VGPRs: two 512-thread workgroups must share a CU.
+__global__ __launch_bounds__(kBatchBlockC) __attribute__((amdgpu_waves_per_eu(4))) void k_batch_c128(
     const double2 *__restrict__ mats, const int64_t *__restrict__ offsets,
     const uint32_t *__restrict__ order, const BatchChunk *__restrict__ chunks, uint32_t nchunks,
-    uint32_t *counter, double2 *__restrict__ results, int nmax, const uint16_t *__restrict__ g_masks) {
+    uint32_t *counter, double2 *__restrict__ results, int nmax, const BatchChunk single) {
     extern __shared__ double2 bsm[];
     __shared__ uint32_t s_next;
     uint16_t *s_masks = (uint16_t *)bsm;
     double2 *area = bsm + batch_mask_bytes(nmax) / sizeof(double2);
-    load_masks(s_masks, g_masks, nmax);
-    if (threadIdx.x == 0) s_next = atomicAdd(counter, 1u);
+    load_masks(s_masks);
+    const bool one = single.count != 0;
+    if (threadIdx.x == 0) s_next = one ? 0u : atomicAdd(counter, 1u);
     __syncthreads();
     uint32_t c = s_next;
-    if (c >= nchunks) return;  // uniform: every thread read the same index
-    BatchChunk ch = chunks[c];
+    if (!one && c >= nchunks) return;  // uniform: every thread read the same index
+    BatchChunk ch = one ? single : chunks[c];
     ChunkPrefetch R;
     prefetch_chunk(R, ch, mats, offsets, order);
     __syncthreads();  // everyone has read s_next
     for (;;) {
         // current chunk's matrices into LDS, claim the next chunk
         if (ch.n >= 3) stage_chunk(R, ch, area);
-        if (threadIdx.x == 0) s_next = atomicAdd(counter, 1u);
+        if (threadIdx.x == 0) s_next = one ? 1u : atomicAdd(counter, 1u);
         __syncthreads();
         const uint32_t c2 = s_next;
+        const bool more = !one && c2 < nchunks;
         BatchChunk ch2 = ch;
-        if (c2 < nchunks) {
+        if (more) {
             ch2 = chunks[c2];
             prefetch_chunk(R, ch2, mats, offsets, order);  // in flight during the compute below
         }
@@ -242,17 +251,28 @@ __global__ __launch_bounds__(kBatchBlock) void k_batch_c128(
         case 3: batch_chunk_c128<3>(ch, nmax, s_masks, area, order, results); break;
         default: batch_chunk_tiny_c128(ch, mats, offsets, order, results); break;
         }
-        if (c2 >= nchunks) break;  // uniform
+        if (!more) break;  // uniform
         ch = ch2;
     }
 }
 
 hipError_t launch_batch_c128(const void *mats, const int64_t *offsets, const uint32_t *order,
                              const BatchChunk *chunks, uint32_t nchunks, uint32_t *counter,
-                             void *results, int nmax, const uint16_t *masks, int grid, hipStream_t s) {
+                             void *results, int nmax, int grid, hipStream_t s) {
     const size_t lds = batch_lds_bytes(nmax, 16);
-    hipLaunchKernelGGL(k_batch_c128, dim3(grid), dim3(kBatchBlock), lds, s, (const double2 *)mats,
-                       offsets, order, chunks, nchunks, counter, (double2 *)results, nmax, masks);
+    const BatchChunk none{0, 0, 0, 0};
+    hipLaunchKernelGGL(k_batch_c128, dim3(grid), dim3(kBatchBlockC), lds, s, (const double2 *)mats,
+                       offsets, order, chunks, nchunks, counter, (double2 *)results, nmax, none);
+    return hipGetLastError();
+}
+
+hipError_t launch_single_c128(const void *mat, int n, void *result, hipStream_t s) {
+    const size_t lds = batch_lds_bytes(n, 16);
+    int lg = 0;
+    while ((1 << lg) < kBatchBlockC) lg++;
+    const BatchChunk one{0, 1, (uint8_t)n, (uint8_t)lg};
+    hipLaunchKernelGGL(k_batch_c128, dim3(1), dim3(kBatchBlockC), lds, s, (const double2 *)mat, nullptr,
+                       nullptr, nullptr, 0u, nullptr, (double2 *)result, n, one);
     return hipGetLastError();
 }
 
@@ -273,25 +293,26 @@ __global__ __launch_bounds__(kBatchBlock) void k_batch_modp(
     const int64_t *__restrict__ mats, const int64_t *__restrict__ offsets,
     const uint32_t *__restrict__ order, const BatchChunk *__restrict__ chunks, uint32_t nchunks,
     uint32_t *counter, const uint64_t *__restrict__ primes, int nprimes, uint64_t *__restrict__ res,
-    uint32_t count) {
+    uint32_t count, const BatchChunk single) {
     extern __shared__ uint64_t bsu_all[];
     __shared__ uint32_t s_chunk;
     uint64_t *bsu = bsu_all;
-    for (;;) {
-        if (threadIdx.x == 0) s_chunk = atomicAdd(counter, 1u);
+    const bool one = single.count != 0;
+    for (uint32_t iter = 0;; iter++) {
+        if (threadIdx.x == 0) s_chunk = one ? iter : atomicAdd(counter, 1u);
         __syncthreads();
         const uint32_t c = s_chunk;
         __syncthreads();
-        if (c >= nchunks) break;
-        const BatchChunk ch = chunks[c];
+        if (one ? c >= 1u : c >= nchunks) break;
+        const BatchChunk ch = one ? single : chunks[c];
         const int n = ch.n, lg = ch.group, G = 1 << lg;
         const int gi = threadIdx.x >> lg, lane = threadIdx.x & (G - 1);
         const int per = (1 << n) + n * n;
         uint64_t *tab = bsu + (size_t)gi * per;
         uint64_t *mat = tab + (1 << n);
         const bool active = gi < (int)ch.count;
-        const uint32_t mi = active ? order[ch.first + gi] : 0u;
-        const int64_t *src = mats + (active ? offsets[mi] : 0);
+        const uint32_t mi = active ? (order ? order[ch.first + gi] : ch.first + gi) : 0u;
+        const int64_t *src = mats + (active && offsets ? offsets[mi] : 0);
         for (int r = 0; r < nprimes; r++) {
             const uint64_t p = primes[r];
             if (active) {
@@ -338,9 +359,26 @@ hipError_t launch_batch_modp(const int64_t *mats, const int64_t *offsets, const 
                              const uint64_t *primes, int nprimes, uint64_t *res, uint32_t count,
                              int nmax, int grid, hipStream_t s) {
     const size_t lds = batch_lds_bytes(nmax, 8);
+    const BatchChunk none{0, 0, 0, 0};
     hipLaunchKernelGGL(k_batch_modp, dim3(grid), dim3(kBatchBlock), lds, s, mats, offsets, order,
-                       chunks, nchunks, counter, primes, nprimes, res, count);
+                       chunks, nchunks, counter, primes, nprimes, res, count, none);
     return hipGetLastError();
+}
+
+hipError_t launch_single_modp(const int64_t *mat, int n, const uint64_t *primes, int nprimes, uint64_t *res,
+                              hipStream_t s) {
+    const size_t lds = batch_lds_bytes(n, 8);
+    int lg = 0;
+    while ((1 << lg) < kBatchBlock) lg++;
+    const BatchChunk one{0, 1, (uint8_t)n, (uint8_t)lg};
+    hipLaunchKernelGGL(k_batch_modp, dim3(1), dim3(kBatchBlock), lds, s, mat, nullptr, nullptr, nullptr, 0u,
+                       nullptr, primes, nprimes, res, 1u, one);
+    return hipGetLastError();
+}
+
+hipError_t upload_batch_masks(const uint16_t *host, hipStream_t s) {
+    return hipMemcpyToSymbolAsync(HIP_SYMBOL(g_batch_masks), host, sizeof(uint16_t) << kBatchNMax, 0,
+                                  hipMemcpyHostToDevice, s);
 }
 
 }  // namespace permgpu

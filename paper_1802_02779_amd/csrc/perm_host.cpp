@@ -301,9 +301,10 @@ int tuned_layer_flags(int n) {
     return g_tune.layer_flags[n];
 }
 
-// Threads per matrix in the batched kernel: a power of two in [16, 256]
-// with 256/G matrices fitting the workgroup's LDS.
-int tuned_batch_group(int n, size_t lds_bytes, int elem_bytes) {
+// Threads per matrix in the batched kernel: a power of two in [16, block]
+// with block/G matrices fitting the workgroup's LDS and (complex kernel) its
+// register staging of 4 entries per thread.
+int tuned_batch_group(int n, size_t lds_bytes, int elem_bytes, int block) {
     int g;
     {
         std::lock_guard<std::mutex> lk(g_tune_mu);
@@ -311,13 +312,13 @@ int tuned_batch_group(int n, size_t lds_bytes, int elem_bytes) {
         g = g_tune.batch_group[n];
     }
     if (g == 0) {
-        static const int defaults[PERM_BATCH_N_MAX + 1] = {16, 16, 16, 16, 16, 16, 16, 32, 32, 64, 64, 128, 256};
+        static const int defaults[PERM_BATCH_N_MAX + 1] = {16, 16, 16, 64, 64, 64, 64, 64, 64, 64, 64, 128, 256};
         g = defaults[n];
     }
+    if (g > block) g = block;
     const size_t per = (((size_t)1 << n) + (size_t)n * n) * elem_bytes;
-    while (g < 256 && (size_t)(256 / g) * per > lds_bytes) g *= 2;
-    // the batched kernel stages a chunk's matrices through at most 1024 entries of registers
-    while (g < 256 && (256 / g) * n * n > 1024) g *= 2;
+    while (g < block && (size_t)(block / g) * per > lds_bytes) g *= 2;
+    while (g < block && (block / g) * n * n > 4 * block) g *= 2;
     return g;
 }
 
@@ -382,6 +383,28 @@ int solve_c128_device(int n, const void *a_dev, int64_t lda, void *result_dev, v
     if (rc) return rc;
     char *base = (char *)ws;
     void *packed = base;
+    if (n <= kBatchNMax) {
+        // one launch of the on-chip kernel: the whole table stays in LDS
+        const void *mat = a_dev;
+        if (lda != n) {
+            HIPCALL(launch_pack_c128(a_dev, lda, n, packed, base + align256((size_t)n * n * 16) + 256, s),
+                    "pack kernel");
+            mat = packed;
+        }
+        hipEvent_t e0 = nullptr, e1 = nullptr;
+        const bool prof = profiling_on();
+        if (prof) {
+            e0 = profile_event();
+            e1 = profile_event();
+            if (e0) (void)hipEventRecord(e0, s);
+        }
+        HIPCALL(launch_single_c128(mat, n, result_dev, s), "small-n kernel");
+        if (prof && e0 && e1) {
+            (void)hipEventRecord(e1, s);
+            profile_record(2, e0, e1);
+        }
+        return PERM_OK;
+    }
     const size_t lay = align256(max_layer(n) * 16);
     char *buf0 = base + align256((size_t)n * n * 16) + 256;
     char *buf1 = buf0 + lay;
@@ -463,6 +486,14 @@ static int solve_int(int n, const int64_t *a, int64_t lda, perm_int_t *out, void
 
     HIPCALL(hipMemcpyAsync(d_a, packed.data(), packed.size() * 8, hipMemcpyHostToDevice, s), "upload matrix");
     HIPCALL(hipMemcpyAsync(d_primes, ps.data(), Rt * 8, hipMemcpyHostToDevice, s), "upload primes");
+    if (n <= kBatchNMax) {
+        // one launch of the on-chip kernel for every prime
+        HIPCALL(launch_single_modp(d_a, n, d_primes, Rt, d_res, s), "small-n kernel");
+        std::vector<uint64_t> res(Rt);
+        HIPCALL(hipMemcpyAsync(res.data(), d_res, Rt * 8, hipMemcpyDeviceToHost, s), "download residues");
+        HIPCALL(hipStreamSynchronize(s), "hipStreamSynchronize");
+        return crt_to_int(res.data(), ps.data(), R, out);
+    }
     const int t = tuned_layer_t(n);
     const int chunk = tuned_layer_remap(n);
     const bool prof = profiling_on();
@@ -534,7 +565,7 @@ struct BatchPlan {
     int nmax = 0;
 };
 
-static void build_batch_plan(int count, const int32_t *ns, size_t lds, int elem, BatchPlan &bp) {
+static void build_batch_plan(int count, const int32_t *ns, size_t lds, int elem, int block, BatchPlan &bp) {
     bp.order.resize(count);
     std::iota(bp.order.begin(), bp.order.end(), 0u);
     // largest cost first (cost grows with n); stable keeps input order inside an n
@@ -545,8 +576,8 @@ static void build_batch_plan(int count, const int32_t *ns, size_t lds, int elem,
     int i = 0;
     while (i < count) {
         const int n = ns[bp.order[i]];
-        const int G = tuned_batch_group(n, lds, elem);
-        const int per = 256 / G;
+        const int G = tuned_batch_group(n, lds, elem, block);
+        const int per = block / G;
         int j = i;
         while (j < count && ns[bp.order[j]] == n && j - i < per) j++;
         BatchChunk c;
@@ -562,7 +593,7 @@ static void build_batch_plan(int count, const int32_t *ns, size_t lds, int elem,
 }
 
 struct BatchLayout {
-    size_t counter, order, offsets, chunks, masks, primes, res, mats, total;
+    size_t counter, order, offsets, chunks, primes, res, mats, total;
 };
 
 static BatchLayout batch_layout(perm_dtype_t dt, int count, const int32_t *ns) {
@@ -576,8 +607,6 @@ static BatchLayout batch_layout(perm_dtype_t dt, int count, const int32_t *ns) {
     off += align256((size_t)count * 8);
     L.chunks = off;
     off += align256((size_t)count * sizeof(BatchChunk));
-    L.masks = off;
-    off += align256((size_t)2 << PERM_BATCH_N_MAX);
     if (dt == PERM_INT64) {
         size_t elems = 0;
         for (int i = 0; i < count; i++) elems += (size_t)ns[i] * ns[i];
@@ -627,7 +656,7 @@ static int batch_c128(int count, const int32_t *ns, const int64_t *offsets, cons
         for (int i = 0; i < count; i++) nmax = std::max(nmax, (int)ns[i]);
         const size_t lds = batch_area_bytes(nmax, 16);
         BatchPlan bp;
-        build_batch_plan(count, ns, lds, 16, bp);
+        build_batch_plan(count, ns, lds, 16, kBatchBlockComplex, bp);
         const uint32_t nchunks = (uint32_t)bp.chunks.size();
         HIPCALL(hipMemcpyAsync(base + L.order, bp.order.data(), (size_t)count * 4, hipMemcpyHostToDevice, s),
                 "upload order");
@@ -636,25 +665,13 @@ static int batch_c128(int count, const int32_t *ns, const int64_t *offsets, cons
         HIPCALL(hipMemcpyAsync(base + L.chunks, bp.chunks.data(), nchunks * sizeof(BatchChunk),
                                hipMemcpyHostToDevice, s),
                 "upload chunks");
-        {
-            static std::mutex mask_mu;
-            static std::vector<uint16_t> mask_lists[PERM_BATCH_N_MAX + 1];
-            std::lock_guard<std::mutex> mlk(mask_mu);
-            auto &ml = mask_lists[nmax];
-            if (ml.empty()) {
-                ml.resize((size_t)1 << nmax);
-                batch_mask_list(nmax, ml.data());
-            }
-            HIPCALL(hipMemcpyAsync(base + L.masks, ml.data(), ml.size() * 2, hipMemcpyHostToDevice, s),
-                    "upload masks");
-        }
         const int grid = std::max(1, std::min<int>((int)nchunks, cu_count() * batch_blocks_per_cu(nmax, 16)));
         auto enqueue = [&](hipStream_t q) -> hipError_t {
             hipError_t e = launch_batch_reset(d_counter, q);
             if (e != hipSuccess) return e;
             return launch_batch_c128(mats, (const int64_t *)(base + L.offsets), (const uint32_t *)(base + L.order),
                                      (const BatchChunk *)(base + L.chunks), nchunks, d_counter, results, nmax,
-                                     (const uint16_t *)(base + L.masks), grid, q);
+                                     grid, q);
         };
         if (!use_graph) {
             glk.unlock();
@@ -750,7 +767,7 @@ static int batch_int(int count, const int32_t *ns, const int64_t *offsets, const
     for (int i = 0; i < count; i++) nmax = std::max(nmax, (int)ns[i]);
     const size_t lds = batch_lds_bytes(nmax, 8) - 64;
     BatchPlan bp;
-    build_batch_plan(count, ns, lds, 8, bp);
+    build_batch_plan(count, ns, lds, 8, kBatchBlockInt, bp);
     const uint32_t nchunks = (uint32_t)bp.chunks.size();
     char *base = (char *)ws;
     const auto &ps = primes61();
@@ -930,8 +947,9 @@ int perm_tuning_set(const perm_tuning_t *in) {
     }
     for (int n = 0; n <= PERM_BATCH_N_MAX; n++) {
         const int g = in->batch_group[n];
-        if (g != 0 && (g < 16 || g > 256 || (g & (g - 1))))
-            return set_error(PERM_EINVAL, "batch_group[%d] = %d (power of two in 16..256)", n, g);
+        if (g != 0 && (g < 16 || g > kBatchBlockComplex || (g & (g - 1))))
+            return set_error(PERM_EINVAL, "batch_group[%d] = %d (power of two in 16..%d)", n, g,
+                             kBatchBlockComplex);
     }
     std::lock_guard<std::mutex> lk(g_tune_mu);
     g_tune = *in;

@@ -29,6 +29,8 @@ constexpr int kHighBits = 17;    // largest high part (columns) of a tile
 constexpr int kBatchNMax = 12;   // largest order of the on-chip batched kernel
 constexpr int kRPMax = 3;        // primes that share one integer sweep
 constexpr int kMaxGroups = 32;   // k' groups in one layer launch
+constexpr int kBatchBlockComplex = 512;  // threads of a complex batched workgroup
+constexpr int kBatchBlockInt = 256;      // threads of an integer batched workgroup
 
 struct BinomTable {
     uint32_t v[33][33];
@@ -118,13 +120,20 @@ struct BatchChunk {
     uint32_t first;   // index into the sorted order
     uint16_t count;   // matrices in this chunk (same n)
     uint8_t n;
-    uint8_t group;    // log2 of threads per matrix
+    uint8_t group;    // log2 of threads per matrix (a workgroup holds block / 2^group matrices)
 };
 
 hipError_t launch_batch_reset(uint32_t *counter, hipStream_t s);
 hipError_t launch_batch_c128(const void *mats, const int64_t *offsets, const uint32_t *order,
                              const BatchChunk *chunks, uint32_t nchunks, uint32_t *counter,
-                             void *results, int nmax, const uint16_t *masks, int grid, hipStream_t s);
+                             void *results, int nmax, int grid, hipStream_t s);
+// One matrix of order n (packed row-major at mat, device) through the batched
+// kernel in a single workgroup; writes per(A) to *result (device).
+hipError_t launch_single_c128(const void *mat, int n, void *result, hipStream_t s);
+// Same for residues: res[r] = per(A) mod primes[r], r < nprimes.
+hipError_t launch_single_modp(const int64_t *mat, int n, const uint64_t *primes, int nprimes, uint64_t *res,
+                              hipStream_t s);
+hipError_t upload_batch_masks(const uint16_t *host, hipStream_t s);
 hipError_t launch_batch_modp(const int64_t *mats, const int64_t *offsets, const uint32_t *order,
                              const BatchChunk *chunks, uint32_t nchunks, uint32_t *counter,
                              const uint64_t *primes, int nprimes, uint64_t *res, uint32_t count,

@@ -80,6 +80,14 @@ hipError_t ensure_tables(int device, hipStream_t s) {
     hipLaunchKernelGGL(k_build_highlist, dim3((1u << kHighBits) / 256), dim3(256), 0, s);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
+    static uint16_t masks[1u << kBatchNMax];
+    static bool masks_built = false;
+    if (!masks_built) {
+        batch_mask_list(kBatchNMax, masks);
+        masks_built = true;
+    }
+    e = upload_batch_masks(masks, s);
+    if (e != hipSuccess) return e;
     e = hipStreamSynchronize(s);
     if (e == hipSuccess) g_tables_ready[device] = true;
     return e;

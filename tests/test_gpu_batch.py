@@ -86,7 +86,7 @@ def test_batch_group_variants(P):
     ref = oracle_bits(b)
     saved = P.perm_tuning_get()
     try:
-        for g in (16, 32, 64, 128, 256):
+        for g in (16, 32, 64, 128, 256, 512):
             t = P.perm_tuning_t.from_buffer_copy(saved)
             for n in range(13):
                 t.batch_group[n] = g
