@@ -87,8 +87,12 @@ def main():
     C128 = perm.PERM_COMPLEX128
     tuning_file = os.path.join(ROOT, "paper_1802_02779_amd", "tuning", "gfx950.json")
     tuning = "library defaults"
-    if os.path.exists(tuning_file) and perm.perm_tuning_load(tuning_file) == 0:
-        tuning = os.path.relpath(tuning_file, ROOT)
+    if os.path.exists(tuning_file):
+        try:
+            if perm.perm_tuning_load(tuning_file) == 0:
+                tuning = os.path.relpath(tuning_file, ROOT)
+        except perm.PermError as e:
+            log(f"tuning file ignored: {e}")
     if args.copy_calibration:
         src = torch.empty(1 << 30, dtype=torch.uint8, device="cuda")
         dst = torch.empty_like(src)

@@ -202,12 +202,16 @@ int perm_server_destroy(perm_server_t *s);
  *   layer_xcd_remap[n] tiles dealt to each of the 8 XCDs in runs of this many
  *                      consecutive tiles; 0 = hardware order, -1 = default.
  *   layer_flags[n]     bit 0: non-temporal stores of layer outputs.
+ *   layer_thin[n]      tiles with fewer outputs than this are computed one
+ *                      output per thread instead of staging a window in LDS;
+ *                      0 = library default (128), -1 = never.
  *   batch_group[n]     threads that share one matrix in the batched kernel
  *                      (power of two, 16..512); 0 = library default. */
 typedef struct {
     int layer_t[PERM_N_MAX + 1];
     int layer_xcd_remap[PERM_N_MAX + 1];
     int layer_flags[PERM_N_MAX + 1];
+    int layer_thin[PERM_N_MAX + 1];
     int batch_group[PERM_BATCH_N_MAX + 1];
 } perm_tuning_t;
 

@@ -9,7 +9,7 @@ parameter here only changes the schedule, so any difference would be a bug and
 disqualifies the candidate):
 
 * layer sweep (perm_solve_async, complex128): low-window width t, XCD chunk
-  of the tile order, non-temporal output stores;
+  of the tile order, non-temporal output stores, per-thread threshold;
 * batched kernel (perm_solve_batch, complex128): threads per matrix.
 
 The winners go into the process-wide tuning table (perm_tuning_set) and are
@@ -53,31 +53,36 @@ def tune_layer(perm, inputs, torch, n: int, log=print, reps: int = 3):
     default.layer_t[n] = 0
     default.layer_xcd_remap[n] = -1
     default.layer_flags[n] = 0
+    default.layer_thin[n] = 0
     perm.perm_tuning_set(default)
     run = lambda: perm.perm_solve_async(n, d_a, n, d_r, ws)  # noqa: E731
     ref_ms = _time_ms(run, reps, torch.cuda.synchronize)
     ref = d_r.cpu().numpy().view(np.uint64).copy()
-    best = (ref_ms, 0, -1, 0)
+    best = (ref_ms, 0, -1, 0, 0)
     t_lo, t_hi = max(1, n - 17, n - 19), min(15, n)
     for t in range(max(t_lo, 8), t_hi + 1):
         for chunk in (0, 16, 64, 256):
             for nt in (0, 1):
-                cand = perm.perm_tuning_t.from_buffer_copy(default)
-                cand.layer_t[n] = t
-                cand.layer_xcd_remap[n] = chunk
-                cand.layer_flags[n] = nt
-                perm.perm_tuning_set(cand)
-                ms = _time_ms(run, reps, torch.cuda.synchronize)
-                same = (d_r.cpu().numpy().view(np.uint64) == ref).all()
-                if not same:
-                    log(f"  n={n} t={t} chunk={chunk} nt={nt}: result differs, rejected")
-                    continue
-                if ms < best[0]:
-                    best = (ms, t, chunk, nt)
+                for thin in (-1, 128, 512):
+                    cand = perm.perm_tuning_t.from_buffer_copy(default)
+                    cand.layer_t[n] = t
+                    cand.layer_xcd_remap[n] = chunk
+                    cand.layer_flags[n] = nt
+                    cand.layer_thin[n] = thin
+                    perm.perm_tuning_set(cand)
+                    ms = _time_ms(run, reps, torch.cuda.synchronize)
+                    same = (d_r.cpu().numpy().view(np.uint64) == ref).all()
+                    if not same:
+                        log(f"  n={n} t={t} chunk={chunk} nt={nt} thin={thin}: result differs, rejected")
+                        continue
+                    if ms < best[0]:
+                        best = (ms, t, chunk, nt, thin)
     final = perm.perm_tuning_t.from_buffer_copy(base)
-    final.layer_t[n], final.layer_xcd_remap[n], final.layer_flags[n] = best[1], best[2], best[3]
+    (final.layer_t[n], final.layer_xcd_remap[n], final.layer_flags[n],
+     final.layer_thin[n]) = best[1], best[2], best[3], best[4]
     perm.perm_tuning_set(final)
-    log(f"layer n={n}: default {ref_ms:.3f} ms -> t={best[1]} chunk={best[2]} nt={best[3]} {best[0]:.3f} ms")
+    log(f"layer n={n}: default {ref_ms:.3f} ms -> t={best[1]} chunk={best[2]} nt={best[3]} "
+        f"thin={best[4]} {best[0]:.3f} ms")
     return best
 
 

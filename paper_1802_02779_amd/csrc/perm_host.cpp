@@ -295,6 +295,14 @@ int tuned_layer_remap(int n) {
     return r >= 0 ? r : (n >= 20 ? 64 : 0);
 }
 
+// Tiles with fewer outputs than this go to the per-thread path.
+uint32_t tuned_layer_thin(int n) {
+    std::lock_guard<std::mutex> lk(g_tune_mu);
+    tune_init_locked();
+    const int v = g_tune.layer_thin[n];
+    return v < 0 ? 0u : (v == 0 ? 128u : (uint32_t)v);
+}
+
 int tuned_layer_flags(int n) {
     std::lock_guard<std::mutex> lk(g_tune_mu);
     tune_init_locked();
@@ -416,7 +424,7 @@ int solve_c128_device(int n, const void *a_dev, int64_t lda, void *result_dev, v
     char *prev = buf0, *next = buf1;
     for (int k = 2; k <= n; k++) {
         LayerArgs args;
-        const uint32_t grid = plan_layer(n, k, t, chunk, nt, &args);
+        const uint32_t grid = plan_layer(n, k, t, chunk, nt, tuned_layer_thin(n), &args);
         hipEvent_t e0 = nullptr, e1 = nullptr;
         if (prof) {
             e0 = profile_event();
@@ -509,7 +517,7 @@ static int solve_int(int n, const int64_t *a, int64_t lda, perm_int_t *out, void
         uint64_t *prev = buf0, *next = buf1;
         for (int k = 2; k <= n; k++) {
             LayerArgs args;
-            const uint32_t grid = plan_layer(n, k, t, chunk, 0, &args);
+            const uint32_t grid = plan_layer(n, k, t, chunk, 0, 0, &args);
             args.binary_row = binary[k - 1];
             hipEvent_t e0 = nullptr, e1 = nullptr;
             if (prof) {
@@ -944,6 +952,8 @@ int perm_tuning_set(const perm_tuning_t *in) {
             return set_error(PERM_EINVAL, "layer_xcd_remap[%d] = %d", n, in->layer_xcd_remap[n]);
         if (in->layer_flags[n] & ~1)
             return set_error(PERM_EINVAL, "layer_flags[%d] = %d", n, in->layer_flags[n]);
+        if (in->layer_thin[n] < -1 || in->layer_thin[n] > 65536)
+            return set_error(PERM_EINVAL, "layer_thin[%d] = %d", n, in->layer_thin[n]);
     }
     for (int n = 0; n <= PERM_BATCH_N_MAX; n++) {
         const int g = in->batch_group[n];
@@ -1009,11 +1019,24 @@ int perm_tuning_load(const char *path) {
     if (s.find(want) == std::string::npos) return set_error(PERM_ENOTFOUND, "tuning file is for another device");
     perm_tuning_t t;
     std::memset(&t, 0, sizeof t);
-    if (!json_int_array(s, "layer_t", t.layer_t, PERM_N_MAX + 1) ||
-        !json_int_array(s, "layer_xcd_remap", t.layer_xcd_remap, PERM_N_MAX + 1) ||
-        !json_int_array(s, "layer_flags", t.layer_flags, PERM_N_MAX + 1) ||
-        !json_int_array(s, "batch_group", t.batch_group, PERM_BATCH_N_MAX + 1))
-        return set_error(PERM_EINVAL, "malformed tuning file %s", path);
+    for (int n = 0; n <= PERM_N_MAX; n++) t.layer_xcd_remap[n] = -1;
+    // every array is optional (a file from an older library lacks the newer
+    // ones: those keep their defaults); a present array must be complete
+    struct {
+        const char *name;
+        int *v;
+        int cnt;
+    } arrays[] = {{"layer_t", t.layer_t, PERM_N_MAX + 1},
+                  {"layer_xcd_remap", t.layer_xcd_remap, PERM_N_MAX + 1},
+                  {"layer_flags", t.layer_flags, PERM_N_MAX + 1},
+                  {"layer_thin", t.layer_thin, PERM_N_MAX + 1},
+                  {"batch_group", t.batch_group, PERM_BATCH_N_MAX + 1}};
+    for (auto &a : arrays) {
+        const std::string pat = std::string("\"") + a.name + "\"";
+        if (s.find(pat) == std::string::npos) continue;
+        if (!json_int_array(s, a.name, a.v, a.cnt))
+            return set_error(PERM_EINVAL, "malformed array %s in tuning file %s", a.name, path);
+    }
     return perm_tuning_set(&t);
 }
 
@@ -1035,6 +1058,7 @@ int perm_tuning_save(const char *path) {
     arr("layer_t", t.layer_t, PERM_N_MAX + 1, false);
     arr("layer_xcd_remap", t.layer_xcd_remap, PERM_N_MAX + 1, false);
     arr("layer_flags", t.layer_flags, PERM_N_MAX + 1, false);
+    arr("layer_thin", t.layer_thin, PERM_N_MAX + 1, false);
     arr("batch_group", t.batch_group, PERM_BATCH_N_MAX + 1, true);
     std::fprintf(f, "}\n");
     std::fclose(f);

@@ -24,6 +24,7 @@ int prepare_device(hipStream_t s, int *device);
 int tuned_layer_t(int n);
 int tuned_layer_remap(int n);
 int tuned_layer_flags(int n);
+uint32_t tuned_layer_thin(int n);
 int tuned_batch_group(int n, size_t lds_bytes, int elem_bytes, int block);
 
 // Complex solve of a device matrix into a device result, stream-ordered.

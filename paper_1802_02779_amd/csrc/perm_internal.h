@@ -87,11 +87,21 @@ struct LayerArgs {
     uint32_t ck[kMaxGroups];         // C(t, k'): outputs per tile
     uint32_t low_off[kMaxGroups];    // lowtab offset of (t, k')
     uint32_t high_off[kMaxGroups];   // highlist offset of popcount m = k - k'
+    // Groups whose tiles have fewer than `thin_below` outputs are not tiled:
+    // workgroups past big_blocks give one output to each thread instead.
+    uint32_t big_blocks;
+    int thin_groups;
+    int32_t t_kp[kMaxGroups];
+    uint32_t t_ck[kMaxGroups];
+    uint32_t t_out_start[kMaxGroups + 1];  // prefix sums of the thin groups' outputs
+    uint32_t t_low_off[kMaxGroups];
+    uint32_t t_high_off[kMaxGroups];
 };
 
-// Fills LayerArgs for layer k of order n with low window t; returns the
-// number of tiles (grid size).
-uint32_t plan_layer(int n, int k, int t, int chunk, int nt_store, LayerArgs *a);
+// Fills LayerArgs for layer k of order n with low window t; groups with
+// fewer than thin_below outputs per tile go to the per-thread path.
+// Returns the grid size (tiled workgroups + per-thread workgroups).
+uint32_t plan_layer(int n, int k, int t, int chunk, int nt_store, uint32_t thin_below, LayerArgs *a);
 
 // Dynamic LDS bytes of a layer launch.
 size_t layer_lds_bytes_c128(const LayerArgs &a);

@@ -94,7 +94,7 @@ hipError_t ensure_tables(int device, hipStream_t s) {
 }
 
 // -------------------------------------------------------------- planning
-uint32_t plan_layer(int n, int k, int t, int chunk, int nt_store, LayerArgs *a) {
+uint32_t plan_layer(int n, int k, int t, int chunk, int nt_store, uint32_t thin_below, LayerArgs *a) {
     const int nh = n - t;
     a->n = n;
     a->k = k;
@@ -103,27 +103,43 @@ uint32_t plan_layer(int n, int k, int t, int chunk, int nt_store, LayerArgs *a) 
     a->nt_store = nt_store;
     a->binary_row = 0;
     a->ngroups = 0;
+    a->thin_groups = 0;
     a->lds_window = 0;
-    uint32_t tiles = 0;
+    uint32_t tiles = 0, thin_out = 0;
     const int kp_lo = k - nh > 0 ? k - nh : 0;
     const int kp_hi = k < t ? k : t;
     for (int kp = kp_lo; kp <= kp_hi; kp++) {
         const int m = k - kp;
+        const uint32_t ck = binom_host(t, kp);
+        if (ck < thin_below) {
+            const int g = a->thin_groups++;
+            a->t_kp[g] = kp;
+            a->t_ck[g] = ck;
+            a->t_out_start[g] = thin_out;
+            a->t_low_off[g] = lowtab_t_base(t) + lowtab_kp_off(t, kp);
+            a->t_high_off[g] = highlist_off(m);
+            thin_out += binom_host(nh, m) * ck;
+            continue;
+        }
         const int g = a->ngroups++;
         a->kp[g] = kp;
         a->start[g] = tiles;
-        a->ck[g] = binom_host(t, kp);
+        a->ck[g] = ck;
         a->low_off[g] = lowtab_t_base(t) + lowtab_kp_off(t, kp);
         a->high_off[g] = highlist_off(m);
         tiles += binom_host(nh, m);
         if (kp >= 1 && binom_host(t, kp - 1) > a->lds_window) a->lds_window = binom_host(t, kp - 1);
     }
     a->start[a->ngroups] = tiles;
-    return tiles;
+    a->t_out_start[a->thin_groups] = thin_out;
+    a->big_blocks = tiles;
+    return tiles + (thin_out + 255) / 256;
 }
 
 size_t layer_lds_bytes_c128(const LayerArgs &a) {
-    return (size_t)(a.lds_window + a.t + 32) * 16 + 32 * 4;
+    const size_t tiled = (size_t)(a.lds_window + a.t + 32) * 16 + 32 * 4;
+    const size_t thin = 33 * 33 * 4 + 32 * 16;
+    return tiled > thin ? tiled : thin;
 }
 
 size_t layer_lds_bytes_modp(const LayerArgs &a, int rp) {
@@ -150,7 +166,7 @@ struct TileInfo {
 
 __device__ __forceinline__ TileInfo decode_tile(const LayerArgs &A) {
     TileInfo ti;
-    const uint32_t tile = xcd_chunk_remap(blockIdx.x, gridDim.x, (uint32_t)A.chunk);
+    const uint32_t tile = xcd_chunk_remap(blockIdx.x, A.big_blocks, (uint32_t)A.chunk);
     int g = 0;
     while (g + 1 < A.ngroups && A.start[g + 1] <= tile) g++;
     ti.g = g;
@@ -212,11 +228,74 @@ hipError_t launch_pack_c128(const void *a_dev, int64_t lda, int n, void *packed,
 
 constexpr int kLayerBlock = 256;
 
+// Per-thread path for groups whose tiles are too small to fill a workgroup:
+// each thread computes one whole output.  Low predecessors come through the
+// rank table from the tile's window (small, cached), high predecessors from
+// the aligned windows (neighbouring threads read neighbouring entries).
+__device__ void layer_c128_thin(const double2 *__restrict__ prev, double2 *__restrict__ next,
+                                const double2 *__restrict__ A, const LayerArgs &args, double2 *smem) {
+    uint32_t *s_bin = (uint32_t *)smem;               // C(i, j) at [i * 33 + j]
+    double2 *s_arow = (double2 *)(s_bin + 33 * 33);   // row k-1 of A
+    const int tid = threadIdx.x;
+    for (int i = tid; i < 33 * 33; i += kLayerBlock) s_bin[i] = c_binom.v[i / 33][i % 33];
+    if (tid < args.n) s_arow[tid] = A[(size_t)(args.k - 1) * args.n + tid];
+    __syncthreads();
+    const uint32_t gid = (blockIdx.x - args.big_blocks) * kLayerBlock + tid;
+    if (gid >= args.t_out_start[args.thin_groups]) return;
+    int g = 0;
+    while (g + 1 < args.thin_groups && args.t_out_start[g + 1] <= gid) g++;
+    const int kp = args.t_kp[g], t = args.t;
+    const uint32_t ck = args.t_ck[g], local = gid - args.t_out_start[g];
+    const uint32_t tile = local / ck, r = local - tile * ck;
+    const uint32_t T = g_highlist[args.t_high_off[g] + tile];
+    // ranks: output base, low-window base, and the base of the first high window
+    uint32_t base_out = 0, base_low = 0, base_h = 0;
+    {
+        uint32_t b = T;
+        for (int i = 1; b; i++) {
+            const int h = __ffs(b) - 1 + t;
+            b &= b - 1;
+            base_out += s_bin[h * 33 + kp + i];
+            base_low += s_bin[h * 33 + kp + i - 1];
+            if (i >= 2) base_h += s_bin[h * 33 + kp + i - 1];
+        }
+    }
+    double re = 0.0, im = 0.0;
+    const uint32_t *lt = g_lowtab + args.t_low_off[g];
+    for (int p = 0; p < kp; p++) {
+        const uint32_t e = lt[(uint32_t)p * ck + r];
+        cfma(re, im, s_arow[e >> 16], prev[base_low + (e & 0xffffu)]);
+    }
+    // high columns ascending; the window that removes the q-th one starts at
+    // base_q, with base_{q+1} = base_q + C(h_q, k'+q) - C(h_{q+1}, k'+q)
+    uint32_t b = T;
+    int q = 1, hprev = 0;
+    while (b) {
+        const int h = __ffs(b) - 1 + t;
+        b &= b - 1;
+        if (q > 1) base_h = base_h + s_bin[hprev * 33 + kp + q - 1] - s_bin[h * 33 + kp + q - 1];
+        cfma(re, im, s_arow[h], prev[base_h + r]);
+        hprev = h;
+        q++;
+    }
+    double2 *out = next + base_out + r;
+    if (args.nt_store) {
+        __builtin_nontemporal_store(re, &out->x);
+        __builtin_nontemporal_store(im, &out->y);
+    } else {
+        *out = make_double2(re, im);
+    }
+}
+
 __global__ __launch_bounds__(kLayerBlock) void k_layer_c128(const double2 *__restrict__ prev,
                                                             double2 *__restrict__ next,
                                                             const double2 *__restrict__ A,
                                                             const LayerArgs args) {
     extern __shared__ double2 smem[];
+    if (blockIdx.x >= args.big_blocks) {
+        layer_c128_thin(prev, next, A, args, smem);
+        return;
+    }
     const int tid = threadIdx.x;
     const TileInfo ti = decode_tile(args);
     const int t = args.t;

@@ -90,6 +90,7 @@ class perm_tuning_t(ctypes.Structure):
     _fields_ = [("layer_t", ctypes.c_int * (PERM_N_MAX + 1)),
                 ("layer_xcd_remap", ctypes.c_int * (PERM_N_MAX + 1)),
                 ("layer_flags", ctypes.c_int * (PERM_N_MAX + 1)),
+                ("layer_thin", ctypes.c_int * (PERM_N_MAX + 1)),
                 ("batch_group", ctypes.c_int * (PERM_BATCH_N_MAX + 1))]
 
 

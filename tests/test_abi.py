@@ -149,3 +149,9 @@ def test_server_config_validation(perm):
     assert L.perm_server_create(None, ctypes.byref(h)) == perm.PERM_EINVAL
     assert L.perm_server_destroy(None) == perm.PERM_EINVAL
     assert L.perm_server_poll(None, 1, None, None) == perm.PERM_EINVAL
+
+
+def test_tuning_file_optional_arrays(perm, tmp_path):
+    # perm_tuning_load checks the device key first, so only the CPU-side
+    # parser behaviour that needs no device is exercised here: a missing file
+    assert perm.perm_tuning_load(str(tmp_path / "missing.json")) == perm.PERM_ENOTFOUND

@@ -168,13 +168,14 @@ def test_determinism_and_tuning_variants(P):
     saved = P.perm_tuning_get()
     try:
         for t in range(3, 16):
-            for remap in (0, 1, 3, 16, 64):
+            for remap, thin in ((0, -1), (1, 0), (3, 5000), (16, 64), (64, 16)):
                 tu = P.perm_tuning_t.from_buffer_copy(saved)
                 tu.layer_t[n] = t
                 tu.layer_xcd_remap[n] = remap
                 tu.layer_flags[n] = remap & 1
+                tu.layer_thin[n] = thin
                 P.perm_tuning_set(tu)
-                assert c_bits(P.perm_solve(A)) == ref, (t, remap)
+                assert c_bits(P.perm_solve(A)) == ref, (t, remap, thin)
     finally:
         P.perm_tuning_set(saved)
     for _ in range(5):
