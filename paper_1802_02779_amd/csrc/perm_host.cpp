@@ -517,7 +517,7 @@ static int solve_int(int n, const int64_t *a, int64_t lda, perm_int_t *out, void
         uint64_t *prev = buf0, *next = buf1;
         for (int k = 2; k <= n; k++) {
             LayerArgs args;
-            const uint32_t grid = plan_layer(n, k, t, chunk, 0, 0, &args);
+            const uint32_t grid = plan_layer(n, k, t, chunk, 0, tuned_layer_thin(n), &args);
             args.binary_row = binary[k - 1];
             hipEvent_t e0 = nullptr, e1 = nullptr;
             if (prof) {

@@ -143,7 +143,9 @@ size_t layer_lds_bytes_c128(const LayerArgs &a) {
 }
 
 size_t layer_lds_bytes_modp(const LayerArgs &a, int rp) {
-    return (size_t)rp * (a.lds_window + a.t + 32) * 8 + 32 * 4;
+    const size_t tiled = (size_t)rp * (a.lds_window + a.t + 32) * 8 + 32 * 4;
+    const size_t thin = (33 * 33 + 1) * 4 + (size_t)rp * 32 * 8;
+    return tiled > thin ? tiled : thin;
 }
 
 // XCD-aware order.  Workgroup b is dispatched to XCD b % 8 as that XCD's
@@ -412,6 +414,85 @@ hipError_t launch_reduce_modp(const int64_t *a_dev, int n, const uint64_t *prime
     return hipGetLastError();
 }
 
+// Per-thread path of the integer sweep (see layer_c128_thin).
+template <int RP, bool BIN>
+__device__ void layer_modp_thin(const uint64_t *__restrict__ prev, uint64_t *__restrict__ next, size_t plane,
+                                const uint64_t *__restrict__ red, const uint64_t *__restrict__ primes,
+                                const LayerArgs &args, uint64_t *smem) {
+    uint32_t *s_bin = (uint32_t *)smem;                 // C(i, j) at [i * 33 + j]
+    uint64_t *s_arow = (uint64_t *)(s_bin + 33 * 33 + 1);  // RP x 32 residues of row k-1 (8-byte aligned)
+    const int tid = threadIdx.x, n = args.n;
+    for (int i = tid; i < 33 * 33; i += kLayerBlock) s_bin[i] = c_binom.v[i / 33][i % 33];
+    if (tid < n) {
+#pragma unroll
+        for (int r = 0; r < RP; r++) s_arow[r * 32 + tid] = red[(size_t)r * n * n + (size_t)(args.k - 1) * n + tid];
+    }
+    __syncthreads();
+    const uint32_t gid = (blockIdx.x - args.big_blocks) * kLayerBlock + tid;
+    if (gid >= args.t_out_start[args.thin_groups]) return;
+    int g = 0;
+    while (g + 1 < args.thin_groups && args.t_out_start[g + 1] <= gid) g++;
+    const int kp = args.t_kp[g], t = args.t;
+    const uint32_t ck = args.t_ck[g], local = gid - args.t_out_start[g];
+    const uint32_t tile = local / ck, rr = local - tile * ck;
+    const uint32_t T = g_highlist[args.t_high_off[g] + tile];
+    uint32_t base_out = 0, base_low = 0, base_h = 0;
+    {
+        uint32_t b = T;
+        for (int i = 1; b; i++) {
+            const int h = __ffs(b) - 1 + t;
+            b &= b - 1;
+            base_out += s_bin[h * 33 + kp + i];
+            base_low += s_bin[h * 33 + kp + i - 1];
+            if (i >= 2) base_h += s_bin[h * 33 + kp + i - 1];
+        }
+    }
+    u128 acc[RP];
+#pragma unroll
+    for (int r = 0; r < RP; r++) acc[r] = 0;
+    const uint32_t *lt = g_lowtab + args.t_low_off[g];
+    for (int p = 0; p < kp; p++) {
+        const uint32_t e = lt[(uint32_t)p * ck + rr];
+        const uint32_t idx = base_low + (e & 0xffffu), col = e >> 16;
+        if (BIN) {
+            if (s_arow[col] != 0) {
+#pragma unroll
+                for (int r = 0; r < RP; r++) acc[r] += prev[(size_t)r * plane + idx];
+            }
+        } else {
+#pragma unroll
+            for (int r = 0; r < RP; r++) {
+                const uint64_t a = s_arow[r * 32 + col];
+                if (a != 0) acc[r] += (u128)a * prev[(size_t)r * plane + idx];
+            }
+        }
+    }
+    uint32_t b = T;
+    int q = 1, hprev = 0;
+    while (b) {
+        const int h = __ffs(b) - 1 + t;
+        b &= b - 1;
+        if (q > 1) base_h = base_h + s_bin[hprev * 33 + kp + q - 1] - s_bin[h * 33 + kp + q - 1];
+        const uint32_t idx = base_h + rr;
+        if (BIN) {
+            if (s_arow[h] != 0) {
+#pragma unroll
+                for (int r = 0; r < RP; r++) acc[r] += prev[(size_t)r * plane + idx];
+            }
+        } else {
+#pragma unroll
+            for (int r = 0; r < RP; r++) {
+                const uint64_t a = s_arow[r * 32 + h];
+                if (a != 0) acc[r] += (u128)a * prev[(size_t)r * plane + idx];
+            }
+        }
+        hprev = h;
+        q++;
+    }
+#pragma unroll
+    for (int r = 0; r < RP; r++) next[(size_t)r * plane + base_out + rr] = fold61(acc[r], primes[r]);
+}
+
 // BIN: every entry of this layer's row of A is 0 or 1 (then equal in every
 // residue), so a term is either skipped or a plain addition.
 template <int RP, bool BIN>
@@ -421,6 +502,10 @@ __global__ __launch_bounds__(kLayerBlock) void k_layer_modp(const uint64_t *__re
                                                             const uint64_t *__restrict__ primes,
                                                             const LayerArgs args) {
     extern __shared__ uint64_t smem_u[];
+    if (blockIdx.x >= args.big_blocks) {
+        layer_modp_thin<RP, BIN>(prev, next, plane, red, primes, args, smem_u);
+        return;
+    }
     const int tid = threadIdx.x;
     const TileInfo ti = decode_tile(args);
     const int t = args.t, n = args.n;
