@@ -2,4 +2,6 @@
 // the rank tables (binomials, popcount-ordered masks) built for the layer
 // sweep, so both are compiled together.
 #include "perm_layers.hip"
+#include "perm_layer_c128.hip"
+#include "perm_layer_modp.hip"
 #include "perm_batch.hip"

@@ -40,14 +40,24 @@ if __name__ == "__main__" and not (len(sys.argv) > 1 and sys.argv[1] == "counter
     main()
 
 
-def source_hash(root: str) -> str:
-    """Hash of the layer-sweep sources: counter data is valid only for them."""
+def source_hash(root: str, n: int = 28) -> str:
+    """Hash of what decides the complex layer sweep's memory traffic at order
+    n: its kernel sources and the order-n entries of the shipped tuning file.
+    Counter data is valid only while this hash is unchanged."""
     import hashlib
+    import json
     import os
     h = hashlib.sha256()
-    for f in ("perm_layers.hip", "perm_internal.h"):
-        with open(os.path.join(root, "paper_1802_02779_amd", "csrc", f), "rb") as fh:
+    csrc = os.path.join(root, "paper_1802_02779_amd", "csrc")
+    for f in ("perm_layers.hip", "perm_layer_c128.hip", "perm_internal.h"):
+        with open(os.path.join(csrc, f), "rb") as fh:
             h.update(fh.read())
+    tfile = os.path.join(root, "paper_1802_02779_amd", "tuning", "gfx950.json")
+    if os.path.exists(tfile):
+        with open(tfile) as fh:
+            t = json.load(fh)
+        row = [t.get(k, [0] * (n + 1))[n] for k in ("layer_t", "layer_xcd_remap", "layer_flags", "layer_thin")]
+        h.update(repr(row).encode())
     return h.hexdigest()[:16]
 
 
