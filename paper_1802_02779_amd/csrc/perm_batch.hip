@@ -20,7 +20,9 @@ __device__ uint16_t g_batch_masks[1u << kBatchNMax];
 
 constexpr int kBatchBlock = 256;   // integer batched kernel
 constexpr int kBatchBlockC = kBatchBlockComplex;  // complex batched kernel
-constexpr size_t kBatchLdsCap = 70 * 1024;  // with the mask list: two workgroups per CU
+// Matrix area per workgroup: four order-10 matrices (4 * (2^10 + 100) * 16 B);
+// with the 8 KB mask list two workgroups still share a CU's 160 KB.
+constexpr size_t kBatchLdsCap = 4 * ((1 << 10) + 100) * 16;
 
 __device__ __forceinline__ uint32_t bbinom(int i, int j) { return c_binom.v[i][j]; }
 
@@ -42,11 +44,15 @@ __device__ __forceinline__ void bcfma(double &re, double &im, const double2 a, c
 // (2^n table entries + n*n matrix entries) each.
 __host__ __device__ size_t batch_mask_bytes(int) { return ((size_t)2 << kBatchNMax) + 16; }
 
+// The complex kernel always takes the whole cap: its 512-thread workgroups
+// at 128 VGPRs are limited to two per CU by registers anyway, and a larger
+// area lets a chunk hold more small matrices.  The integer kernel (256
+// threads) keeps its area near its need so that more workgroups fit a CU.
 size_t batch_area_bytes(int nmax, int elem_bytes) {
     if (nmax < 0) nmax = 0;
     const size_t per = ((size_t)1 << nmax) + (size_t)nmax * nmax;
     size_t need = per * elem_bytes;
-    if (need < kBatchLdsCap) need = kBatchLdsCap < 4 * need ? kBatchLdsCap : 4 * need;
+    if (need < kBatchLdsCap) need = (elem_bytes == 16 || kBatchLdsCap < 4 * need) ? kBatchLdsCap : 4 * need;
     return need;
 }
 
@@ -77,7 +83,7 @@ __device__ __forceinline__ uint32_t mask_block(int nmax, int k) {
 
 // The mask list (built on the host, see batch_mask_list) is copied into LDS
 // once per workgroup.
-__device__ void load_masks(uint16_t *s_masks) {
+__device__ __forceinline__ void load_masks(uint16_t *s_masks) {
     for (uint32_t i = threadIdx.x; i < (1u << kBatchNMax); i += blockDim.x) s_masks[i] = g_batch_masks[i];
 }
 
@@ -97,16 +103,16 @@ constexpr int cbinom(int n, int k) {
 // One chunk of matrices of order N.  Layer by layer, each lane computes whole
 // stored values F(S) with the fixed chain over columns in ascending order;
 // the column loop is unrolled and the row of A is held in registers.
+// mi is the result index of this thread's matrix (read with the prefetch).
 template <int N>
 __device__ __forceinline__ void batch_chunk_c128(const BatchChunk ch, int nmax, const uint16_t *s_masks, double2 *area,
-                                                 const uint32_t *__restrict__ order, double2 *__restrict__ results) {
+                                                 uint32_t mi, double2 *__restrict__ results) {
     const int lg = ch.group, G = 1 << lg;
     const int gi = threadIdx.x >> lg, lane = threadIdx.x & (G - 1);
     constexpr int PER = (1 << N) + N * N;
     double2 *tab = area + (size_t)gi * PER;
     double2 *mat = tab + (1 << N);
     const bool active = gi < (int)ch.count;
-    const uint32_t mi = active ? (order ? order[ch.first + gi] : ch.first + gi) : 0u;  // used at the end
     if (active)
         for (int j = lane; j < N; j += G) tab[cpos<N>(1u << j)] = mat[j];
     __syncthreads();
@@ -118,10 +124,14 @@ __device__ __forceinline__ void batch_chunk_c128(const BatchChunk ch, int nmax, 
 #pragma unroll
             for (int j = 0; j < N; j++) a[j] = mat[(k - 1) * N + j];
             const int cnt = cbinom(N, k);
+            // the mask of the lane's next entry is read one round ahead, and
+            // all predecessor loads go to distinct registers before the chain
+            // starts, so each round waits for LDS once
+            uint32_t Sn = lane < cnt ? ml[lane] : 0u;
             for (int i = lane; i < cnt; i += G) {
-                const uint32_t S = ml[i];
+                const uint32_t S = Sn;
+                if (i + G < cnt) Sn = ml[i + G];
                 const double2 *t0 = tab + cpos<N>(S);
-                // all predecessor loads first (independent), then the chain;
                 // a column outside S contributes no term
                 double2 p[N];
 #pragma unroll
@@ -150,7 +160,7 @@ __device__ __forceinline__ void batch_chunk_tiny_c128(const BatchChunk ch, const
                                       double2 *__restrict__ results) {
     for (uint32_t g = threadIdx.x; g < ch.count; g += blockDim.x) {
         const uint32_t mi = order ? order[ch.first + g] : ch.first + g;
-        const double2 *a = mats + (offsets ? offsets[mi] : 0);
+        const double2 *a = mats + (offsets ? offsets[ch.first + g] : 0);
         double2 r;
         if (ch.n == 0) {
             r = make_double2(1.0, 0.0);
@@ -168,91 +178,145 @@ __device__ __forceinline__ void batch_chunk_tiny_c128(const BatchChunk ch, const
 }
 
 // Entries of a chunk's matrices staged through registers: thread i holds
-// flat entries i, i + 256, ... (at most kPrefetch of them; the planner keeps
-// (B / G) * n * n <= B * kPrefetch for the workgroup size B).
-constexpr int kPrefetch = 4;
-
+// flat entry i (the planner keeps (B / G) * n * n <= B for the workgroup size
+// B), so the whole next chunk is in flight in four registers, together with
+// the result index of the thread's matrix.
 struct ChunkPrefetch {
-    double2 v[kPrefetch];
+    double2 v;
+    uint32_t mi;
+    int64_t off;  // element offset of the matrix holding flat entry threadIdx.x
 };
+
+// offsets[] is in work-list order (entry ch.first + g is the chunk's g-th
+// matrix).  Two phases: the offset and result index of the thread's matrix
+// first, then (once the offset has arrived) the matrix entry itself.
+__device__ __forceinline__ void prefetch_index(ChunkPrefetch &R, const BatchChunk ch,
+                                               const int64_t *__restrict__ offsets,
+                                               const uint32_t *__restrict__ order) {
+    const uint32_t nn = (uint32_t)ch.n * ch.n, tot = nn * ch.count, f = threadIdx.x;
+    R.off = 0;
+    if (f < tot && offsets) R.off = offsets[ch.first + f / nn];
+    const uint32_t gi = threadIdx.x >> ch.group;
+    R.mi = gi < ch.count ? (order ? order[ch.first + gi] : ch.first + gi) : 0u;
+}
+
+__device__ __forceinline__ void prefetch_entry(ChunkPrefetch &R, const BatchChunk ch,
+                                               const double2 *__restrict__ mats) {
+    const uint32_t nn = (uint32_t)ch.n * ch.n, tot = nn * ch.count, f = threadIdx.x;
+    if (f < tot) R.v = mats[R.off + (f - (f / nn) * nn)];
+}
 
 __device__ __forceinline__ void prefetch_chunk(ChunkPrefetch &R, const BatchChunk ch,
                                                const double2 *__restrict__ mats,
                                                const int64_t *__restrict__ offsets,
                                                const uint32_t *__restrict__ order) {
-    const uint32_t nn = (uint32_t)ch.n * ch.n, tot = nn * ch.count;
-#pragma unroll
-    for (int r = 0; r < kPrefetch; r++) {
-        const uint32_t f = threadIdx.x + (uint32_t)r * kBatchBlockC;
-        if (f < tot) {
-            const uint32_t g = f / nn, e = f - g * nn;
-            const uint32_t mi = order ? order[ch.first + g] : ch.first + g;
-            R.v[r] = mats[(offsets ? offsets[mi] : 0) + e];
-        }
-    }
+    prefetch_index(R, ch, offsets, order);
+    prefetch_entry(R, ch, mats);
 }
 
 __device__ __forceinline__ void stage_chunk(const ChunkPrefetch &R, const BatchChunk ch, double2 *area) {
-    const uint32_t nn = (uint32_t)ch.n * ch.n, tot = nn * ch.count;
-    const uint32_t per = (1u << ch.n) + nn;
-#pragma unroll
-    for (int r = 0; r < kPrefetch; r++) {
-        const uint32_t f = threadIdx.x + (uint32_t)r * kBatchBlockC;
-        if (f < tot) {
-            const uint32_t g = f / nn, e = f - g * nn;
-            area[(size_t)g * per + (1u << ch.n) + e] = R.v[r];
-        }
+    const uint32_t nn = (uint32_t)ch.n * ch.n, tot = nn * ch.count, f = threadIdx.x;
+    if (f < tot) {
+        const uint32_t g = f / nn, e = f - g * nn;
+        area[(size_t)g * ((1u << ch.n) + nn) + (1u << ch.n) + e] = R.v;
     }
+}
+
+// Chunk descriptors travel as two raw words: loaded with a vector load (its
+// latency is tracked apart from LDS traffic) and made wave-uniform only
+// where they are used.
+__device__ __forceinline__ uint2 chunk_raw(const BatchChunk *chunks, uint32_t c) {
+    return *reinterpret_cast<const uint2 *>(chunks + c);
+}
+
+__device__ __forceinline__ BatchChunk chunk_from(uint2 w) {
+    BatchChunk c;
+    c.first = __builtin_amdgcn_readfirstlane(w.x);
+    const uint32_t y = __builtin_amdgcn_readfirstlane(w.y);
+    c.count = (uint16_t)(y & 0xffffu);
+    c.n = (uint8_t)((y >> 16) & 0xffu);
+    c.group = (uint8_t)(y >> 24);
+    return c;
 }
 
 // With single.count == 1 the launch solves that one chunk (matrix 0 at
 // offset 0, no work list, no counter); otherwise it runs the persistent loop.
+// The loop is pipelined so that no round trip to memory sits between two
+// chunks: while chunk i is computed, the matrices of chunk i+1 are in flight
+// to registers, the descriptor of chunk i+2 is being read and the index of
+// chunk i+3 is being claimed from the counter.  A claimed index at or beyond
+// nchunks means the list is exhausted; since the counter only grows, a
+// workgroup that stops holds no unprocessed chunk.
 // At most 128 VGPRs: two 512-thread workgroups must share a CU.
 __global__ __launch_bounds__(kBatchBlockC) __attribute__((amdgpu_waves_per_eu(4))) void k_batch_c128(
     const double2 *__restrict__ mats, const int64_t *__restrict__ offsets,
-    const uint32_t *__restrict__ order, const BatchChunk *__restrict__ chunks, uint32_t nchunks,
+    const uint32_t *__restrict__ order, const BatchChunk *chunks, uint32_t nchunks,
     uint32_t *counter, double2 *__restrict__ results, int nmax, const BatchChunk single) {
     extern __shared__ double2 bsm[];
-    __shared__ uint32_t s_next;
+    __shared__ uint32_t s_claim;
     uint16_t *s_masks = (uint16_t *)bsm;
     double2 *area = bsm + batch_mask_bytes(nmax) / sizeof(double2);
     load_masks(s_masks);
     const bool one = single.count != 0;
-    if (threadIdx.x == 0) s_next = one ? 0u : atomicAdd(counter, 1u);
+    const uint32_t nch = one ? 1u : nchunks;
+    if (threadIdx.x == 0 && !one) s_claim = atomicAdd(counter, 3u);  // indices c, c + 1, c + 2
     __syncthreads();
-    uint32_t c = s_next;
-    if (!one && c >= nchunks) return;  // uniform: every thread read the same index
-    BatchChunk ch = one ? single : chunks[c];
+    const uint32_t c0 = one ? 0u : __builtin_amdgcn_readfirstlane(s_claim);
+    if (c0 >= nch) return;  // uniform
+    BatchChunk ch = one ? single : chunk_from(chunk_raw(chunks, c0));
+    bool have1 = c0 + 1 < nch;
+    BatchChunk ch1 = ch;
+    if (have1) ch1 = chunk_from(chunk_raw(chunks, c0 + 1));
+    uint32_t c2 = c0 + 2;
     ChunkPrefetch R;
     prefetch_chunk(R, ch, mats, offsets, order);
-    __syncthreads();  // everyone has read s_next
+    __syncthreads();  // everyone has read s_claim
     for (;;) {
-        // current chunk's matrices into LDS, claim the next chunk
+        // staging waits for the registers filled by the previous prefetch;
+        // everything issued after it stays in flight during the compute
         if (ch.n >= 3) stage_chunk(R, ch, area);
-        if (threadIdx.x == 0) s_next = one ? 1u : atomicAdd(counter, 1u);
-        __syncthreads();
-        const uint32_t c2 = s_next;
-        const bool more = !one && c2 < nchunks;
-        BatchChunk ch2 = ch;
-        if (more) {
-            ch2 = chunks[c2];
-            prefetch_chunk(R, ch2, mats, offsets, order);  // in flight during the compute below
-        }
+        const uint32_t mi = R.mi;
+        // nothing newer than the previous prefetch is in flight here; settling
+        // it on every path (orders <= 2 skip the staging) keeps the compiler
+        // from waiting for the loads below when it refills R
+        __builtin_amdgcn_s_waitcnt(0x0f70);  // vmcnt(0)
+        // next chunk: its offsets and result indices, then the descriptor
+        // after it (index clamped to the list, so the load needs no branch of
+        // its own; the single-matrix launch has no list), then its matrix
+        // entries, then the claim; all stay in flight during the compute
+        if (have1) prefetch_index(R, ch1, offsets, order);
+        const bool have2 = c2 < nch;
+        uint2 d2 = make_uint2(0u, 0u);
+        if (!one) d2 = chunk_raw(chunks, have2 ? c2 : 0u);  // decoded after the compute
+        if (have1) prefetch_entry(R, ch1, mats);
+        // atomicInc (not atomicAdd) keeps the compiler from turning this
+        // single-lane claim into a wave-wide pattern that waits for it here
+        uint32_t claimed = 0;
+        if (threadIdx.x == 0 && !one) claimed = atomicInc(counter, 0xffffffffu);  // used after the compute
+        __syncthreads();  // the staged matrices are visible to every thread
         switch (ch.n) {
-        case 12: batch_chunk_c128<12>(ch, nmax, s_masks, area, order, results); break;
-        case 11: batch_chunk_c128<11>(ch, nmax, s_masks, area, order, results); break;
-        case 10: batch_chunk_c128<10>(ch, nmax, s_masks, area, order, results); break;
-        case 9: batch_chunk_c128<9>(ch, nmax, s_masks, area, order, results); break;
-        case 8: batch_chunk_c128<8>(ch, nmax, s_masks, area, order, results); break;
-        case 7: batch_chunk_c128<7>(ch, nmax, s_masks, area, order, results); break;
-        case 6: batch_chunk_c128<6>(ch, nmax, s_masks, area, order, results); break;
-        case 5: batch_chunk_c128<5>(ch, nmax, s_masks, area, order, results); break;
-        case 4: batch_chunk_c128<4>(ch, nmax, s_masks, area, order, results); break;
-        case 3: batch_chunk_c128<3>(ch, nmax, s_masks, area, order, results); break;
+        case 12: batch_chunk_c128<12>(ch, nmax, s_masks, area, mi, results); break;
+        case 11: batch_chunk_c128<11>(ch, nmax, s_masks, area, mi, results); break;
+        case 10: batch_chunk_c128<10>(ch, nmax, s_masks, area, mi, results); break;
+        case 9: batch_chunk_c128<9>(ch, nmax, s_masks, area, mi, results); break;
+        case 8: batch_chunk_c128<8>(ch, nmax, s_masks, area, mi, results); break;
+        case 7: batch_chunk_c128<7>(ch, nmax, s_masks, area, mi, results); break;
+        case 6: batch_chunk_c128<6>(ch, nmax, s_masks, area, mi, results); break;
+        case 5: batch_chunk_c128<5>(ch, nmax, s_masks, area, mi, results); break;
+        case 4: batch_chunk_c128<4>(ch, nmax, s_masks, area, mi, results); break;
+        case 3: batch_chunk_c128<3>(ch, nmax, s_masks, area, mi, results); break;
         default: batch_chunk_tiny_c128(ch, mats, offsets, order, results); break;
         }
-        if (!more) break;  // uniform
-        ch = ch2;
+        // every chunk body ends with a barrier, so all reads of the previous
+        // s_claim are done before it is overwritten here
+        if (threadIdx.x == 0) s_claim = claimed;
+        __syncthreads();
+        const uint32_t c3 = one ? nch : __builtin_amdgcn_readfirstlane(s_claim);
+        if (!have1) break;  // uniform
+        ch = ch1;
+        if (have2) ch1 = chunk_from(d2);
+        have1 = have2;
+        c2 = c3;
     }
 }
 

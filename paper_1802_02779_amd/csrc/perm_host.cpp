@@ -310,8 +310,9 @@ int tuned_layer_flags(int n) {
 }
 
 // Threads per matrix in the batched kernel: a power of two in [16, block]
-// with block/G matrices fitting the workgroup's LDS and (complex kernel) its
-// register staging of 4 entries per thread.
+// with block/G matrices fitting the workgroup's LDS and, for the complex
+// kernel, its register staging of one matrix entry per thread (the integer
+// kernel reads its matrices directly; it keeps at most 4 entries per thread).
 int tuned_batch_group(int n, size_t lds_bytes, int elem_bytes, int block) {
     int g;
     {
@@ -326,7 +327,8 @@ int tuned_batch_group(int n, size_t lds_bytes, int elem_bytes, int block) {
     if (g > block) g = block;
     const size_t per = (((size_t)1 << n) + (size_t)n * n) * elem_bytes;
     while (g < block && (size_t)(block / g) * per > lds_bytes) g *= 2;
-    while (g < block && (block / g) * n * n > 4 * block) g *= 2;
+    const int stage = elem_bytes == 16 ? 1 : 4;
+    while (g < block && (block / g) * n * n > stage * block) g *= 2;
     return g;
 }
 
@@ -668,7 +670,10 @@ static int batch_c128(int count, const int32_t *ns, const int64_t *offsets, cons
         const uint32_t nchunks = (uint32_t)bp.chunks.size();
         HIPCALL(hipMemcpyAsync(base + L.order, bp.order.data(), (size_t)count * 4, hipMemcpyHostToDevice, s),
                 "upload order");
-        HIPCALL(hipMemcpyAsync(base + L.offsets, offsets, (size_t)count * 8, hipMemcpyHostToDevice, s),
+        // the kernel reads offsets in work-list order (one dependent load fewer)
+        std::vector<int64_t> soff(count);
+        for (int i = 0; i < count; i++) soff[i] = offsets[bp.order[i]];
+        HIPCALL(hipMemcpyAsync(base + L.offsets, soff.data(), (size_t)count * 8, hipMemcpyHostToDevice, s),
                 "upload offsets");
         HIPCALL(hipMemcpyAsync(base + L.chunks, bp.chunks.data(), nchunks * sizeof(BatchChunk),
                                hipMemcpyHostToDevice, s),
