@@ -239,14 +239,45 @@ __device__ __forceinline__ BatchChunk chunk_from(uint2 w) {
     return c;
 }
 
+// Chunks are claimed from the counter in groups of kClaimGroup consecutive
+// chunks (group q covers chunks q*K .. q*K+K-1): fewer trips to the shared
+// counter, while the group size stays small next to the list so that faster
+// workgroups still take more of the work.  The list is sorted by cost, so
+// the last groups hold the cheapest chunks.
+constexpr uint32_t kClaimGroup = 4;
+
+// Index sequence of one workgroup: the chunks of its current group, then of
+// the next claimed group.  Two claimed groups are kept ahead of the current
+// one; taking one out of that queue issues a claim for its replacement, whose
+// value arrives at the end of the same loop iteration.
+struct ChunkSeq {
+    uint32_t q, j;    // group and position of the last index handed out
+    uint32_t f0, f1;  // the two claimed groups that follow
+    uint32_t K, nch;
+    // next index (>= nch once the list is exhausted); sets pop when it moved
+    // into a new group
+    __device__ __forceinline__ uint32_t next(bool &pop) {
+        if (j + 1 < K && q * K + j + 1 < nch) {
+            j++;
+            pop = false;
+        } else {
+            q = f0;
+            f0 = f1;
+            j = 0;
+            pop = true;
+        }
+        return q * K + j;
+    }
+};
+
 // With single.count == 1 the launch solves that one chunk (matrix 0 at
 // offset 0, no work list, no counter); otherwise it runs the persistent loop.
 // The loop is pipelined so that no round trip to memory sits between two
 // chunks: while chunk i is computed, the matrices of chunk i+1 are in flight
-// to registers, the descriptor of chunk i+2 is being read and the index of
-// chunk i+3 is being claimed from the counter.  A claimed index at or beyond
-// nchunks means the list is exhausted; since the counter only grows, a
-// workgroup that stops holds no unprocessed chunk.
+// to registers, the descriptor of chunk i+2 is being read and, when chunk i+2
+// opened a new group, the claim of a further group is in flight.  A claimed
+// index at or beyond nchunks means the list is exhausted; since the counter
+// only grows, a workgroup that stops holds no unprocessed chunk.
 // At most 128 VGPRs: two 512-thread workgroups must share a CU.
 __global__ __launch_bounds__(kBatchBlockC) __attribute__((amdgpu_waves_per_eu(4))) void k_batch_c128(
     const double2 *__restrict__ mats, const int64_t *__restrict__ offsets,
@@ -259,18 +290,35 @@ __global__ __launch_bounds__(kBatchBlockC) __attribute__((amdgpu_waves_per_eu(4)
     load_masks(s_masks);
     const bool one = single.count != 0;
     const uint32_t nch = one ? 1u : nchunks;
-    if (threadIdx.x == 0 && !one) s_claim = atomicAdd(counter, 3u);  // indices c, c + 1, c + 2
+    if (threadIdx.x == 0 && !one) s_claim = atomicAdd(counter, 3u);  // groups q, q + 1, q + 2
     __syncthreads();
-    const uint32_t c0 = one ? 0u : __builtin_amdgcn_readfirstlane(s_claim);
-    if (c0 >= nch) return;  // uniform
+    const uint32_t q0 = one ? 0u : __builtin_amdgcn_readfirstlane(s_claim);
+    ChunkSeq seq{q0, 0u, q0 + 1, q0 + 2, one ? 1u : kClaimGroup, nch};
+    const uint32_t c0 = q0 * seq.K;
+    if (c0 >= nch) return;  // uniform: every thread read the same index
+    bool pop1, pop2;
+    const uint32_t c1 = seq.next(pop1);
+    uint32_t c2 = seq.next(pop2);
+    const uint32_t pops = (pop1 ? 1u : 0u) + (pop2 ? 1u : 0u);
+    __syncthreads();  // everyone has read s_claim
+    if (pops && !one) {  // refill the queue of claimed groups (start-up only)
+        if (threadIdx.x == 0) s_claim = atomicAdd(counter, pops);
+        __syncthreads();
+        const uint32_t base = __builtin_amdgcn_readfirstlane(s_claim);
+        if (pops == 2) {
+            seq.f0 = base;
+            seq.f1 = base + 1;
+        } else {
+            seq.f1 = base;
+        }
+        __syncthreads();  // everyone has read s_claim
+    }
     BatchChunk ch = one ? single : chunk_from(chunk_raw(chunks, c0));
-    bool have1 = c0 + 1 < nch;
+    bool have1 = c1 < nch;
     BatchChunk ch1 = ch;
-    if (have1) ch1 = chunk_from(chunk_raw(chunks, c0 + 1));
-    uint32_t c2 = c0 + 2;
+    if (have1) ch1 = chunk_from(chunk_raw(chunks, c1));
     ChunkPrefetch R;
     prefetch_chunk(R, ch, mats, offsets, order);
-    __syncthreads();  // everyone has read s_claim
     for (;;) {
         // staging waits for the registers filled by the previous prefetch;
         // everything issued after it stays in flight during the compute
@@ -280,19 +328,22 @@ __global__ __launch_bounds__(kBatchBlockC) __attribute__((amdgpu_waves_per_eu(4)
         // it on every path (orders <= 2 skip the staging) keeps the compiler
         // from waiting for the loads below when it refills R
         __builtin_amdgcn_s_waitcnt(0x0f70);  // vmcnt(0)
-        // next chunk: its offsets and result indices, then the descriptor
-        // after it (index clamped to the list, so the load needs no branch of
-        // its own; the single-matrix launch has no list), then its matrix
-        // entries, then the claim; all stay in flight during the compute
+        // next chunk: its offsets and result indices, then the descriptor of
+        // the one after it (index clamped to the list, so the load needs no
+        // branch of its own; the single-matrix launch has no list), then its
+        // matrix entries, then a claim if a group was taken from the queue;
+        // all stay in flight during the compute
         if (have1) prefetch_index(R, ch1, offsets, order);
         const bool have2 = c2 < nch;
         uint2 d2 = make_uint2(0u, 0u);
         if (!one) d2 = chunk_raw(chunks, have2 ? c2 : 0u);  // decoded after the compute
         if (have1) prefetch_entry(R, ch1, mats);
+        bool pop;
+        const uint32_t c3 = seq.next(pop);
         // atomicInc (not atomicAdd) keeps the compiler from turning this
         // single-lane claim into a wave-wide pattern that waits for it here
         uint32_t claimed = 0;
-        if (threadIdx.x == 0 && !one) claimed = atomicInc(counter, 0xffffffffu);  // used after the compute
+        if (pop && !one && threadIdx.x == 0) claimed = atomicInc(counter, 0xffffffffu);  // used after the compute
         __syncthreads();  // the staged matrices are visible to every thread
         switch (ch.n) {
         case 12: batch_chunk_c128<12>(ch, nmax, s_masks, area, mi, results); break;
@@ -307,11 +358,13 @@ __global__ __launch_bounds__(kBatchBlockC) __attribute__((amdgpu_waves_per_eu(4)
         case 3: batch_chunk_c128<3>(ch, nmax, s_masks, area, mi, results); break;
         default: batch_chunk_tiny_c128(ch, mats, offsets, order, results); break;
         }
-        // every chunk body ends with a barrier, so all reads of the previous
-        // s_claim are done before it is overwritten here
-        if (threadIdx.x == 0) s_claim = claimed;
-        __syncthreads();
-        const uint32_t c3 = one ? nch : __builtin_amdgcn_readfirstlane(s_claim);
+        if (pop && !one) {  // uniform
+            // every chunk body ends with a barrier, so all reads of the
+            // previous s_claim are done before it is overwritten here
+            if (threadIdx.x == 0) s_claim = claimed;
+            __syncthreads();
+            seq.f1 = __builtin_amdgcn_readfirstlane(s_claim);
+        }
         if (!have1) break;  // uniform
         ch = ch1;
         if (have2) ch1 = chunk_from(d2);

@@ -321,7 +321,10 @@ int tuned_batch_group(int n, size_t lds_bytes, int elem_bytes, int block) {
         g = g_tune.batch_group[n];
     }
     if (g == 0) {
-        static const int defaults[PERM_BATCH_N_MAX + 1] = {16, 16, 16, 64, 64, 64, 64, 64, 64, 64, 64, 128, 256};
+        // as few threads per matrix as the LDS area and the register staging
+        // allow (the loops below raise it): chunks carry as many matrices as
+        // possible, and each chunk costs a claim and a prefetch round trip
+        static const int defaults[PERM_BATCH_N_MAX + 1] = {16, 16, 16, 16, 16, 16, 16, 16, 16, 16, 16, 16, 16};
         g = defaults[n];
     }
     if (g > block) g = block;
