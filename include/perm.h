@@ -126,6 +126,31 @@ int perm_solve_async(int n, const perm_c128_t *a_dev, int64_t lda, perm_c128_t *
 #define PERM_BATCH_REUSE 4u  /* ns/offsets are the same as in the previous call with this
                               * workspace: skip rebuilding and re-uploading the work list */
 
+/* ----------------------------------------------------------- Ryser --- */
+
+/* The permanent by Ryser's inclusion-exclusion formula (eq. 4 of the paper,
+ * the comparison method of its section 3 and Table 4):
+ *   per(A) = (-1)^n sum_{S subset of columns} (-1)^|S| prod_i sum_{j in S} a_ij,
+ * evaluated with FP64 complex arithmetic over the 2^n subsets in
+ * binary-reflected Gray-code order (one column changes between consecutive
+ * subsets), in fixed per-thread ranges that each start from directly
+ * computed row sums, summed in a fixed order.  O(n^2) memory, no tables; the
+ * result is deterministic but, unlike perm_solve, not a Store-zechin chain:
+ * inclusion-exclusion cancels, so it agrees with perm_solve only to within
+ * the rounding bound derived for it (see the tests).  Complex128 only
+ * (dt = PERM_INT64 returns PERM_EINVAL).
+ *
+ * perm_ryser_workspace_bytes: device workspace needed for order n (0 for a
+ * bad dtype or n outside 0..PERM_N_MAX).
+ * perm_ryser: host matrix a (row-major, a[i*lda + j], perm_c128_t) -> host
+ * *result; synchronizes the stream.  Errors as perm_solve.
+ * perm_ryser_async: device matrix -> device *result_dev, stream-ordered.  */
+size_t perm_ryser_workspace_bytes(perm_dtype_t dt, int n);
+int perm_ryser(perm_dtype_t dt, int n, const void *a, int64_t lda, void *result, void *workspace,
+               size_t ws_bytes, void *stream);
+int perm_ryser_async(int n, const perm_c128_t *a_dev, int64_t lda, perm_c128_t *result_dev, void *workspace,
+                     size_t ws_bytes, void *stream);
+
 /* Device workspace bytes for a batch (host array ns of `count` orders). */
 size_t perm_batch_workspace_bytes(perm_dtype_t dt, int count, const int32_t *ns);
 
@@ -145,7 +170,8 @@ size_t perm_batch_workspace_bytes(perm_dtype_t dt, int count, const int32_t *ns)
  * Complex results are bitwise equal to perm_solve on the same matrix.
  * Stream-ordered unless PERM_BATCH_SYNC is given.  With PERM_BATCH_GRAPH the
  * launch is captured once per (workspace, mats, results, count) and replayed;
- * PERM_BATCH_REUSE then skips the host work entirely. */
+ * PERM_BATCH_REUSE then skips the host work entirely, including the checks of
+ * ns and offsets (done when the graph was captured). */
 int perm_solve_batch(perm_dtype_t dt, int count, const int32_t *ns, const int64_t *offsets,
                      const void *mats, void *results, void *workspace, size_t ws_bytes,
                      void *stream, uint32_t flags);
@@ -237,6 +263,8 @@ typedef struct {
     int64_t layer_modp_launches;
     double batch_ms;
     int64_t batch_launches;
+    double ryser_ms;        /* transpose + Gray-code walk + final sum, per call */
+    int64_t ryser_launches;
 } perm_profile_t;
 
 int perm_profile_enable(int on);

@@ -61,6 +61,8 @@ def _load() -> ctypes.CDLL:
             lib.oracle_per_modp.argtypes = [ctypes.c_int, up, ctypes.c_uint64, ctypes.c_int,
                                             ctypes.c_int, up]
             lib.oracle_per_modp.restype = ctypes.c_int
+            lib.oracle_ryser_bound.argtypes = [ctypes.c_int, dp, ctypes.c_int, ctypes.c_int, ctypes.c_int, dp]
+            lib.oracle_ryser_bound.restype = ctypes.c_int
             lib.oracle_max_threads.argtypes = []
             lib.oracle_max_threads.restype = ctypes.c_int
             _lib = lib
@@ -108,6 +110,21 @@ def per_abs(A, nthreads: int = 0) -> float:
     rc = _load().oracle_per_abs(n, flat.ctypes.data_as(ctypes.POINTER(ctypes.c_double)),
                                 nthreads, out.ctypes.data_as(ctypes.POINTER(ctypes.c_double)))
     _check(rc, "oracle_per_abs")
+    return float(out[0])
+
+
+def ryser_bound(A, mm: int, depth: int, nthreads: int = 0) -> float:
+    """Rigorous bound on the rounding error of an fp64 evaluation of Ryser's
+    eq. (4) with ranges of at most 2^mm one-column-change subsets, FMA complex
+    products, and every product passing through at most `depth` additions
+    (derivation in perm_oracle.c).  n <= 24."""
+    A = _as_c128(A)
+    n = A.shape[0]
+    out = np.zeros(1, dtype=np.float64)
+    flat = A.view(np.float64)
+    rc = _load().oracle_ryser_bound(n, flat.ctypes.data_as(ctypes.POINTER(ctypes.c_double)), int(mm), int(depth),
+                                    nthreads, out.ctypes.data_as(ctypes.POINTER(ctypes.c_double)))
+    _check(rc, "oracle_ryser_bound")
     return float(out[0])
 
 

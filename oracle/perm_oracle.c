@@ -41,6 +41,12 @@
  *   |A| (per of entrywise moduli, for the complex tolerance): the complex
  *     chain's real part with a = |a_ij| (hypot) and non-negative values.
  *
+ * Ryser's formula (eq. 4 of the paper, section 3) is the comparison method:
+ *   per(A) = (-1)^n sum_{S} (-1)^|S| prod_i r_i(S),  r_i(S) = sum_{j in S} a_ij.
+ * Its exact value is pinned in the Python oracle; here oracle_ryser_bound
+ * gives a rigorous bound on the rounding error of an fp64 evaluation of it
+ * (see that function).
+ *
  * Build: gcc -O2 -ffp-contract=off -fno-fast-math -fopenmp -shared -fPIC.
  * Returns 0 on success, -1 on bad arguments, -2 when memory runs out.
  */
@@ -307,4 +313,73 @@ int oracle_max_threads(void)
 #else
     return 1;
 #endif
+}
+
+/* ------------------------------------------------------------ Ryser bound */
+/*
+ * Upper bound E on |computed - per(A)| for an fp64 complex evaluation of
+ * eq. (4) (unit roundoff u = 2^-53) that
+ *   (a) splits the 2^n subsets into ranges of at most 2^mm consecutive
+ *       subsets of a one-column-change order, forms the row sums of each
+ *       range's first subset directly (at most n additions) and then changes
+ *       them by one column per subset with one rounding each;
+ *   (b) multiplies the n row sums with complex products whose components
+ *       are each rounded twice (a product, then a fused multiply-add), in
+ *       any order;
+ *   (c) adds the 2^n signed products with every product passing through at
+ *       most `depth` additions.
+ * Error model, with B_i = sum_j |a_ij| and r_i(S) the exact row sums:
+ *   each component of a computed row sum is off by at most
+ *   (gamma_n + 2^mm u) B_i, so |computed r_i - r_i| <= eps_i
+ *   = sqrt(2) (gamma_n + 2^mm u) B_i  (gamma_k = k u / (1 - k u));
+ *   one complex product has relative error at most eta = 2 sqrt(2) u
+ *   (each component: two roundings of terms bounded by |a| |b|, whose sum is
+ *   at most |a||b| by Cauchy-Schwarz), so a computed product is within
+ *   ((1+eta)^(n-1) - 1) prod(|r_i| + eps_i) of the product of the computed
+ *   row sums;
+ *   summation adds at most sqrt(2) gamma_depth times the sum of the moduli.
+ * Hence, with T(S) = (1+eta)^(n-1) prod_i (|r_i(S)| + eps_i),
+ *   E = sum_S [T(S) - prod_i |r_i(S)|] + sqrt(2) gamma_depth sum_S T(S).
+ * The row sums here are themselves computed in fp64 (directly, at most n
+ * additions), so eps_i is enlarged by sqrt(2) gamma_n B_i to cover them, and
+ * the result is multiplied by 1.01 for the rounding of this computation.
+ */
+static double gamma_k(double k) { const double u = ldexp(1.0, -53); return k * u / (1.0 - k * u); }
+
+int oracle_ryser_bound(int n, const double *a, int mm, int depth, int nthreads, double *out)
+{
+    if (n < 1 || n > 24 || !a || !out || mm < 0 || mm > 40 || depth < 0) return -1;
+    const double u = ldexp(1.0, -53);
+    double eps[ORACLE_N_MAX];
+    for (int i = 0; i < n; i++) {
+        double b = 0.0;
+        for (int j = 0; j < n; j++) b += hypot(a[2 * (i * n + j)], a[2 * (i * n + j) + 1]);
+        b *= 1.0 + gamma_k(n + 1);  /* the sum above is itself rounded */
+        eps[i] = sqrt(2.0) * (2.0 * gamma_k(n) + ldexp(1.0, mm) * u) * b;
+    }
+    const double grow = pow(1.0 + 2.0 * sqrt(2.0) * u, n - 1);
+    const uint32_t full = (uint32_t)1 << n;
+    double excess = 0.0, total = 0.0;
+#ifdef _OPENMP
+    if (nthreads > 0) omp_set_num_threads(nthreads);
+#endif
+#pragma omp parallel for schedule(static, 4096) reduction(+ : excess, total)
+    for (uint32_t S = 0; S < full; S++) {
+        double t = grow, p = 1.0;
+        for (int i = 0; i < n; i++) {
+            double rr = 0.0, ri = 0.0;
+            for (int j = 0; j < n; j++)
+                if ((S >> j) & 1u) {
+                    rr += a[2 * (i * n + j)];
+                    ri += a[2 * (i * n + j) + 1];
+                }
+            const double m = hypot(rr, ri);
+            t *= m + eps[i];
+            p *= m;
+        }
+        excess += t - p;
+        total += t;
+    }
+    *out = 1.01 * (excess + sqrt(2.0) * gamma_k(depth) * total);
+    return 0;
 }

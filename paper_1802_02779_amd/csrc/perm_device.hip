@@ -5,3 +5,4 @@
 #include "perm_layer_c128.hip"
 #include "perm_layer_modp.hip"
 #include "perm_batch.hip"
+#include "perm_ryser.hip"

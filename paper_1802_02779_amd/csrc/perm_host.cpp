@@ -644,18 +644,25 @@ struct GraphEntry {
 static std::mutex g_graph_mu;
 static std::map<void *, GraphEntry> g_graphs;  // keyed by workspace
 
+// Orders in 0..PERM_BATCH_N_MAX, offsets >= 0, a matrix pointer when any
+// order is positive.
+static int validate_batch(int count, const int32_t *ns, const int64_t *offsets, const void *mats) {
+    bool any_entries = false;
+    for (int i = 0; i < count; i++) {
+        if (ns[i] < 0) return set_error(PERM_EINVAL, "ns[%d] = %d < 0", i, ns[i]);
+        if (ns[i] > PERM_BATCH_N_MAX)
+            return set_error(PERM_ERANGE, "ns[%d] = %d > %d (use perm_solve)", i, ns[i], PERM_BATCH_N_MAX);
+        if (offsets[i] < 0) return set_error(PERM_EINVAL, "offsets[%d] < 0", i);
+        any_entries |= ns[i] > 0;
+    }
+    if (!mats && any_entries) return set_error(PERM_EINVAL, "null matrix pointer");
+    return PERM_OK;
+}
+
 static int batch_c128(int count, const int32_t *ns, const int64_t *offsets, const void *mats, void *results,
                       void *ws, size_t ws_bytes, hipStream_t s, uint32_t flags) {
-    const BatchLayout L = batch_layout(PERM_COMPLEX128, count, ns);
-    if (ws_bytes < L.total)
-        return set_error(PERM_ENOMEM, "batch workspace of %zu bytes < %zu needed", ws_bytes, L.total);
-    int rc = prepare_device(s, nullptr);
-    if (rc) return rc;
-    char *base = (char *)ws;
-    uint32_t *d_counter = (uint32_t *)(base + L.counter);
     const bool use_graph = (flags & PERM_BATCH_GRAPH) != 0;
     const bool reuse = (flags & PERM_BATCH_REUSE) != 0;
-
     std::unique_lock<std::mutex> glk(g_graph_mu);
     GraphEntry *ge = nullptr;
     if (use_graph) {
@@ -664,6 +671,17 @@ static int batch_c128(int count, const int32_t *ns, const int64_t *offsets, cons
             it->second.count == count && reuse)
             ge = &it->second;
     }
+    if (!ge) {
+        const int vrc = validate_batch(count, ns, offsets, mats);
+        if (vrc) return vrc;
+    }
+    const BatchLayout L = batch_layout(PERM_COMPLEX128, count, ns);
+    if (ws_bytes < L.total)
+        return set_error(PERM_ENOMEM, "batch workspace of %zu bytes < %zu needed", ws_bytes, L.total);
+    int rc = prepare_device(s, nullptr);
+    if (rc) return rc;
+    char *base = (char *)ws;
+    uint32_t *d_counter = (uint32_t *)(base + L.counter);
     if (!ge) {
         int nmax = 0;
         for (int i = 0; i < count; i++) nmax = std::max(nmax, (int)ns[i]);
@@ -820,6 +838,73 @@ static int batch_int(int count, const int32_t *ns, const int64_t *offsets, const
     return PERM_OK;
 }
 
+// -------------------------------------------------------------- ryser
+// Threads of the Gray-code walk: 2^hb of them, each over 2^(n-hb) codes.
+// 2^21 threads keep the last wave of workgroups small next to the whole
+// (three workgroups of 256 per CU fit the register budget at n = 28..30);
+// 2^7 codes per thread keep the direct start (n*n additions) near 5 % of a
+// thread's work; small orders use one code per thread.
+static int ryser_high_bits(int n) {
+    int hb = n - 7;
+    const int lo = std::min(n, 12);
+    if (hb < lo) hb = lo;
+    if (hb > 21) hb = 21;
+    return hb;
+}
+
+static uint32_t ryser_blocks(int n) { return (uint32_t)(((1u << ryser_high_bits(n)) + 255u) / 256u); }
+
+// [matrix slot n*n][transposed n*n][partial sums][result], 256-byte aligned
+struct RyserLayout {
+    size_t mat, at, partial, result, total;
+};
+
+static RyserLayout ryser_layout(int n) {
+    RyserLayout L{};
+    const size_t nn = (size_t)n * n * 16;
+    L.mat = 0;
+    L.at = align256(nn);
+    L.partial = L.at + align256(nn);
+    L.result = L.partial + align256((size_t)ryser_blocks(n) * 16);
+    L.total = L.result + 256;
+    return L;
+}
+
+size_t ryser_c128_workspace_bytes(int n) { return n < 1 ? 256 : ryser_layout(n).total; }
+
+// a_dev (device, lda) -> *result_dev (device), stream-ordered
+static int ryser_c128_device(int n, const void *a_dev, int64_t lda, void *result_dev, void *ws, size_t ws_bytes,
+                             hipStream_t s) {
+    const size_t need = ryser_c128_workspace_bytes(n);
+    if (!ws || ws_bytes < need)
+        return set_error(PERM_ENOMEM, "workspace of %zu bytes < %zu needed for n=%d", ws_bytes, need, n);
+    if (n == 0) {
+        static const perm_c128_t one = {1.0, 0.0};
+        HIPCALL(hipMemcpyAsync(result_dev, &one, 16, hipMemcpyHostToDevice, s), "write result");
+        return PERM_OK;
+    }
+    int rc = prepare_device(s, nullptr);
+    if (rc) return rc;
+    const RyserLayout L = ryser_layout(n);
+    char *base = (char *)ws;
+    const int hb = ryser_high_bits(n);
+    hipEvent_t e0 = nullptr, e1 = nullptr;
+    const bool prof = profiling_on();
+    if (prof) {
+        e0 = profile_event();
+        e1 = profile_event();
+        if (e0) (void)hipEventRecord(e0, s);
+    }
+    HIPCALL(launch_ryser_transpose_c128(a_dev, lda, n, base + L.at, s), "ryser transpose");
+    HIPCALL(launch_ryser_c128(base + L.at, n, n - hb, base + L.partial, ryser_blocks(n), result_dev, s),
+            "ryser kernel");
+    if (prof && e0 && e1) {
+        (void)hipEventRecord(e1, s);
+        profile_record(3, e0, e1);
+    }
+    return PERM_OK;
+}
+
 }  // namespace permgpu
 
 // ======================================================================
@@ -905,6 +990,65 @@ int perm_solve_async(int n, const perm_c128_t *a_dev, int64_t lda, perm_c128_t *
     }
 }
 
+size_t perm_ryser_workspace_bytes(perm_dtype_t dt, int n) {
+    if (n < 0 || n > PERM_N_MAX) return 0;
+    if (dt == PERM_COMPLEX128) return ryser_c128_workspace_bytes(n);
+    return 0;
+}
+
+int perm_ryser(perm_dtype_t dt, int n, const void *a, int64_t lda, void *result, void *workspace,
+               size_t ws_bytes, void *stream) {
+    try {
+        t_err.clear();
+        if (dt != PERM_COMPLEX128) return set_error(PERM_EINVAL, "bad dtype %d for the Ryser path", (int)dt);
+        if (n < 0) return set_error(PERM_EINVAL, "n = %d < 0", n);
+        if (n > PERM_N_MAX) return set_error(PERM_ERANGE, "n = %d > %d", n, PERM_N_MAX);
+        if (!result || (n > 0 && !a)) return set_error(PERM_EINVAL, "null pointer");
+        if (n > 0 && lda < n) return set_error(PERM_EINVAL, "lda = %lld < n = %d", (long long)lda, n);
+        perm_c128_t *out = (perm_c128_t *)result;
+        if (n == 0) {
+            out->re = 1.0;
+            out->im = 0.0;
+            return PERM_OK;
+        }
+        const size_t need = ryser_c128_workspace_bytes(n);
+        if (!workspace || ws_bytes < need)
+            return set_error(PERM_ENOMEM, "workspace of %zu bytes < %zu needed for n=%d", ws_bytes, need, n);
+        hipStream_t s = (hipStream_t)stream;
+        const RyserLayout L = ryser_layout(n);
+        std::vector<perm_c128_t> packed((size_t)n * n);
+        const perm_c128_t *src = (const perm_c128_t *)a;
+        for (int i = 0; i < n; i++)
+            for (int j = 0; j < n; j++) packed[(size_t)i * n + j] = src[(int64_t)i * lda + j];
+        char *base = (char *)workspace;
+        HIPCALL(hipMemcpyAsync(base + L.mat, packed.data(), packed.size() * 16, hipMemcpyHostToDevice, s),
+                "upload matrix");
+        int rc = ryser_c128_device(n, base + L.mat, n, base + L.result, workspace, ws_bytes, s);
+        if (rc) return rc;
+        HIPCALL(hipMemcpyAsync(out, base + L.result, 16, hipMemcpyDeviceToHost, s), "download result");
+        HIPCALL(hipStreamSynchronize(s), "hipStreamSynchronize");
+        return PERM_OK;
+    } catch (const std::exception &e) {
+        return set_error(PERM_EDEVICE, "internal error: %s", e.what());
+    } catch (...) {
+        return set_error(PERM_EDEVICE, "internal error");
+    }
+}
+
+int perm_ryser_async(int n, const perm_c128_t *a_dev, int64_t lda, perm_c128_t *result_dev, void *workspace,
+                     size_t ws_bytes, void *stream) {
+    try {
+        t_err.clear();
+        if (n < 0) return set_error(PERM_EINVAL, "n = %d < 0", n);
+        if (n > PERM_N_MAX) return set_error(PERM_ERANGE, "n = %d > %d", n, PERM_N_MAX);
+        if (!result_dev || (n > 0 && !a_dev)) return set_error(PERM_EINVAL, "null pointer");
+        if (n > 0 && lda < n) return set_error(PERM_EINVAL, "lda = %lld < n = %d", (long long)lda, n);
+        return ryser_c128_device(n, a_dev, lda, result_dev, workspace, ws_bytes, (hipStream_t)stream);
+    } catch (...) {
+        return set_error(PERM_EDEVICE, "internal error");
+    }
+}
+
 size_t perm_batch_workspace_bytes(perm_dtype_t dt, int count, const int32_t *ns) {
     if (count < 0 || (count > 0 && !ns)) return 0;
     if (dt != PERM_COMPLEX128 && dt != PERM_INT64) return 0;
@@ -921,18 +1065,14 @@ int perm_solve_batch(perm_dtype_t dt, int count, const int32_t *ns, const int64_
             return set_error(PERM_EINVAL, "unknown flags 0x%x", flags);
         if (count == 0) return PERM_OK;
         if (!ns || !offsets || !results || !workspace) return set_error(PERM_EINVAL, "null pointer");
-        bool any_entries = false;
-        for (int i = 0; i < count; i++) any_entries |= ns[i] > 0;
-        if (!mats && any_entries) return set_error(PERM_EINVAL, "null matrix pointer");
-        for (int i = 0; i < count; i++) {
-            if (ns[i] < 0) return set_error(PERM_EINVAL, "ns[%d] = %d < 0", i, ns[i]);
-            if (ns[i] > PERM_BATCH_N_MAX)
-                return set_error(PERM_ERANGE, "ns[%d] = %d > %d (use perm_solve)", i, ns[i], PERM_BATCH_N_MAX);
-            if (offsets[i] < 0) return set_error(PERM_EINVAL, "offsets[%d] < 0", i);
-        }
         hipStream_t s = (hipStream_t)stream;
-        if (dt == PERM_INT64)
+        if (dt == PERM_INT64) {
+            const int rc = validate_batch(count, ns, offsets, mats);
+            if (rc) return rc;
             return batch_int(count, ns, offsets, (const int64_t *)mats, (perm_int_t *)results, workspace, ws_bytes, s);
+        }
+        // the complex path validates whenever it builds a work list (a replayed
+        // graph was validated when it was captured)
         return batch_c128(count, ns, offsets, mats, results, workspace, ws_bytes, s, flags);
     } catch (const std::exception &e) {
         return set_error(PERM_EDEVICE, "internal error: %s", e.what());
@@ -1099,9 +1239,12 @@ int perm_profile_read(perm_profile_t *out) {
         } else if (e.kind == 1) {
             out->layer_modp_ms += ms;
             out->layer_modp_launches++;
-        } else {
+        } else if (e.kind == 2) {
             out->batch_ms += ms;
             out->batch_launches++;
+        } else {
+            out->ryser_ms += ms;
+            out->ryser_launches++;
         }
     }
     std::lock_guard<std::mutex> lk(g_prof_mu);

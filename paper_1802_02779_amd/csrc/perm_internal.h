@@ -144,6 +144,14 @@ hipError_t launch_single_c128(const void *mat, int n, void *result, hipStream_t 
 hipError_t launch_single_modp(const int64_t *mat, int n, const uint64_t *primes, int nprimes, uint64_t *res,
                               hipStream_t s);
 hipError_t upload_batch_masks(const uint16_t *host, hipStream_t s);
+
+// ---- Ryser's formula, Gray-code walk (perm_ryser.hip) ----
+// AT (n x n, column j contiguous) from a device matrix with leading dim lda.
+hipError_t launch_ryser_transpose_c128(const void *a_dev, int64_t lda, int n, void *at, hipStream_t s);
+// 2^(n-m) threads of 2^m codes each in `blocks` workgroups of 256 (the
+// last may be partial); partial[blocks] sums, then *out = per(A) (device).
+hipError_t launch_ryser_c128(const void *at, int n, int m, void *partial, uint32_t blocks, void *out,
+                             hipStream_t s);
 hipError_t launch_batch_modp(const int64_t *mats, const int64_t *offsets, const uint32_t *order,
                              const BatchChunk *chunks, uint32_t nchunks, uint32_t *counter,
                              const uint64_t *primes, int nprimes, uint64_t *res, uint32_t count,

@@ -45,7 +45,8 @@ _NAMES = {0: "PERM_OK", 1: "PERM_PENDING", -1: "PERM_EINVAL", -2: "PERM_ERANGE",
 # every symbol the header declares
 EXPORTS = [
     "perm_last_error", "perm_version", "perm_prime", "perm_workspace_bytes", "perm_solve",
-    "perm_solve_async", "perm_batch_workspace_bytes", "perm_solve_batch", "perm_server_create",
+    "perm_solve_async", "perm_ryser_workspace_bytes", "perm_ryser", "perm_ryser_async",
+    "perm_batch_workspace_bytes", "perm_solve_batch", "perm_server_create",
     "perm_server_submit", "perm_server_poll", "perm_server_destroy", "perm_tuning_get",
     "perm_tuning_set", "perm_tuning_load", "perm_tuning_save", "perm_tuning_key",
     "perm_profile_enable", "perm_profile_read",
@@ -97,7 +98,8 @@ class perm_tuning_t(ctypes.Structure):
 class perm_profile_t(ctypes.Structure):
     _fields_ = [("layer_c128_ms", ctypes.c_double), ("layer_c128_launches", ctypes.c_int64),
                 ("layer_modp_ms", ctypes.c_double), ("layer_modp_launches", ctypes.c_int64),
-                ("batch_ms", ctypes.c_double), ("batch_launches", ctypes.c_int64)]
+                ("batch_ms", ctypes.c_double), ("batch_launches", ctypes.c_int64),
+                ("ryser_ms", ctypes.c_double), ("ryser_launches", ctypes.c_int64)]
 
 
 _lock = threading.Lock()
@@ -126,6 +128,12 @@ def lib() -> ctypes.CDLL:
         L.perm_solve.restype = i32
         L.perm_solve_async.argtypes = [i32, vp, i64, vp, vp, sz, vp]
         L.perm_solve_async.restype = i32
+        L.perm_ryser_workspace_bytes.argtypes = [i32, i32]
+        L.perm_ryser_workspace_bytes.restype = sz
+        L.perm_ryser.argtypes = [i32, i32, vp, i64, vp, vp, sz, vp]
+        L.perm_ryser.restype = i32
+        L.perm_ryser_async.argtypes = [i32, vp, i64, vp, vp, sz, vp]
+        L.perm_ryser_async.restype = i32
         L.perm_batch_workspace_bytes.argtypes = [i32, i32, vp]
         L.perm_batch_workspace_bytes.restype = sz
         L.perm_solve_batch.argtypes = [i32, i32, vp, vp, vp, vp, vp, sz, vp, u32]
@@ -239,6 +247,36 @@ def perm_solve_async(n: int, a_dev, lda: int, result_dev, workspace, stream=None
     """Queue per(A) of a device complex128 matrix (torch tensor) into result_dev."""
     ws_bytes = workspace.numel() * workspace.element_size() if workspace is not None else 0
     _check(lib().perm_solve_async(n, a_dev.data_ptr() if a_dev is not None else None, lda,
+                                  result_dev.data_ptr(),
+                                  workspace.data_ptr() if workspace is not None else None, ws_bytes,
+                                  _stream_ptr(stream)))
+
+
+def perm_ryser_workspace_bytes(dtype: int, n: int) -> int:
+    return int(lib().perm_ryser_workspace_bytes(dtype, n))
+
+
+def perm_ryser(A, workspace=None, stream=None) -> complex:
+    """per(A) of a host complex128 matrix by Ryser's formula (eq. 4)."""
+    A = np.ascontiguousarray(np.asarray(A), dtype=np.complex128)
+    if A.ndim != 2 or A.shape[0] != A.shape[1]:
+        raise ValueError("square matrix expected")
+    n = A.shape[0]
+    need = perm_ryser_workspace_bytes(PERM_COMPLEX128, n)
+    ws = workspace if workspace is not None else (device_buffer(need) if n >= 1 else None)
+    ws_ptr = ws.data_ptr() if ws is not None else None
+    ws_bytes = ws.numel() * ws.element_size() if ws is not None else 0
+    s = _stream_ptr(stream) if n >= 1 else None
+    out = perm_c128_t()
+    _check(lib().perm_ryser(PERM_COMPLEX128, n, A.ctypes.data if n else None, max(n, 1), ctypes.byref(out),
+                            ws_ptr, ws_bytes, s))
+    return complex(out.re, out.im)
+
+
+def perm_ryser_async(n: int, a_dev, lda: int, result_dev, workspace, stream=None) -> None:
+    """Queue Ryser's per(A) of a device complex128 matrix into result_dev."""
+    ws_bytes = workspace.numel() * workspace.element_size() if workspace is not None else 0
+    _check(lib().perm_ryser_async(n, a_dev.data_ptr() if a_dev is not None else None, lda,
                                   result_dev.data_ptr(),
                                   workspace.data_ptr() if workspace is not None else None, ws_bytes,
                                   _stream_ptr(stream)))

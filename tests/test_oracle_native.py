@@ -192,3 +192,75 @@ def test_bad_arguments_rejected(oracle_lib):
         oracle_lib.per_c128(np.zeros((31, 31), dtype=np.complex128))
     with pytest.raises(ValueError):
         oracle_lib.per_modp(np.full((3, 3), 7, dtype=np.uint64), 5)
+
+
+# ------------------------------------------------------------ Ryser bound
+def _gray_ryser_fp64(A, mm):
+    """Plain fp64 evaluation of eq. (4) with the structure the bound covers:
+    ranges of 2^mm Gray-code subsets, each starting from directly formed row
+    sums and changing one column per subset; sequential summation."""
+    n = A.shape[0]
+    acc = 0j
+    for x0 in range(0, 1 << n, 1 << mm):
+        S = x0 ^ (x0 >> 1)
+        r = [0j] * n
+        for j in range(n):
+            if (S >> j) & 1:
+                for i in range(n):
+                    r[i] = r[i] + complex(A[i, j])
+        sg = -1.0 if bin(S).count("1") & 1 else 1.0
+        for t in range(1 << mm):
+            if t:
+                j = (t & -t).bit_length() - 1
+                S ^= 1 << j
+                s = 1.0 if (S >> j) & 1 else -1.0
+                for i in range(n):
+                    r[i] = r[i] + s * complex(A[i, j])
+                sg = -sg
+            p = r[0]
+            for v in r[1:]:
+                p = p * v
+            acc = acc + sg * p
+    return acc * (-1) ** n
+
+
+def _exact_complex(A):
+    n = A.shape[0]
+    Q = [[GaussQ(Fraction(float(A[i, j].real)), Fraction(float(A[i, j].imag))) for j in range(n)]
+         for i in range(n)]
+    v = exact.per_store_zechin(Q)
+    return complex(float(v.re), float(v.im))
+
+
+@pytest.mark.parametrize("n,kind", [(5, "gauss"), (6, "gauss"), (7, "gauss"), (6, "huge_column"),
+                                    (7, "scaled_rows")])
+def test_ryser_bound_covers_an_fp64_evaluation(oracle_lib, n, kind):
+    """eq. (4) in fp64 against the exact permanent: the derived bound holds
+    for both a one-range (maximal drift) and a direct (2^0) evaluation, on
+    Gaussian and on badly scaled inputs where cancellation is extreme."""
+    rng = np.random.default_rng(40 + n)
+    A = (rng.standard_normal((n, n)) + 1j * rng.standard_normal((n, n))) / np.sqrt(2)
+    if kind == "huge_column":
+        A[:, 0] *= 1e8
+    elif kind == "scaled_rows":
+        A *= (10.0 ** np.arange(n))[:, None]
+    ref = _exact_complex(A)
+    for mm in (0, n):
+        got = _gray_ryser_fp64(A, mm)
+        bound = oracle_lib.ryser_bound(A, mm, (1 << n) + 1)
+        assert abs(got - ref) <= bound, (n, kind, mm, abs(got - ref), bound)
+
+
+def test_ryser_bound_grows_with_drift_and_depth(oracle_lib):
+    A = inputs.complex_gaussian(8, seed=5)
+    b = [oracle_lib.ryser_bound(A, mm, 64) for mm in (0, 4, 8)]
+    assert b[0] < b[1] < b[2]
+    assert oracle_lib.ryser_bound(A, 2, 16) < oracle_lib.ryser_bound(A, 2, 4096)
+
+
+def test_ryser_bound_scales_with_the_matrix(oracle_lib):
+    """Every term of the bound is homogeneous of degree n in A."""
+    A = inputs.complex_gaussian(7, seed=6)
+    b1 = oracle_lib.ryser_bound(A, 3, 200)
+    b2 = oracle_lib.ryser_bound(2.0 * A, 3, 200)
+    assert b2 == pytest.approx(b1 * 2.0 ** 7, rel=1e-12)
