@@ -51,6 +51,22 @@ def algorithmic_flops(n: int) -> int:
     return 6 * M + 2 * A
 
 
+def ryser_flops(n: int) -> int:
+    """Algorithmic flops of eq. (4) over all 2^n subsets, one column change
+    per subset: n complex additions (2n), n-1 complex multiplications
+    (6 each) and one signed complex accumulation (2)."""
+    return (1 << n) * (2 * n + 6 * (n - 1) + 2)
+
+
+def ryser_issue_bound(n: int) -> float:
+    """Fraction of the FP64 flop peak the instruction mix allows: per subset
+    2n additions (1 flop, 1 instruction), n-1 products of 2 multiplications
+    and 2 fused multiply-adds (6 flops, 4 instructions), 2 fused adds; the
+    peak assumes 2 flops in every issue slot."""
+    instr = 2 * n + 4 * (n - 1) + 2
+    return ryser_flops(n) / (1 << n) / (2.0 * instr)
+
+
 def source_hash() -> str:
     from paper_1802_02779_amd.profiling import source_hash as _h
     return _h(ROOT)
@@ -68,6 +84,9 @@ def main():
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-extras", action="store_true")
+    ap.add_argument("--only", default="",
+                    help="comma list of extra sections to run (n26, ryser, h2h, int30, int10, batch, serving); "
+                         "default: all")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="first copy 1 GiB device to device (a plain copy kernel of known size, "
                          "the reference for HBM byte counters)")
@@ -168,17 +187,36 @@ def main():
     }
 
     if not args.no_extras:
-        result["extras"] = extras(perm, inputs, golden, np, torch, log)
+        only = {x.strip() for x in args.only.split(",") if x.strip()}
+        result["extras"] = extras(perm, inputs, golden, np, torch, log, only)
 
     if not args.no_cpu_baseline:
         result["cpu_baseline"] = cpu_baseline(inputs, log)
     print(json.dumps(result), flush=True)
 
 
-def extras(perm, inputs, golden, np, torch, log):
-    C128 = perm.PERM_COMPLEX128
+def extras(perm, inputs, golden, np, torch, log, only=frozenset()):
     out = {}
-    # configs: 26x26 complex
+    want = lambda name: not only or name in only  # noqa: E731
+    if want("n26"):
+        _extra_n26(perm, inputs, golden, torch, log, out)
+    if want("ryser"):
+        _extra_ryser(perm, inputs, torch, log, out)
+    if want("h2h"):
+        _extra_h2h(perm, inputs, out)
+    if want("int30"):
+        _extra_int30(perm, inputs, golden, log, out)
+    if want("int10"):
+        _extra_int10(perm, inputs, np, out)
+    if want("batch"):
+        _extra_batch(perm, inputs, np, torch, log, out)
+    if want("serving"):
+        out["serving"] = serving(perm, inputs, np, torch, log)
+    return out
+
+
+def _extra_n26(perm, inputs, golden, torch, log, out):
+    C128 = perm.PERM_COMPLEX128
     n = 26
     A = inputs.complex_gaussian(n, seed=0)
     d_a = torch.from_numpy(A).cuda()
@@ -198,7 +236,42 @@ def extras(perm, inputs, golden, np, torch, log):
     log(f"n=26 complex: {ms:.3f} ms")
     del ws
 
-    # host-to-host n = 28 (PCIe-inclusive, for the record)
+
+def _extra_ryser(perm, inputs, torch, log, out):
+    """Ryser's formula (eq. 4), the paper's comparison method, at n = 28."""
+    C128 = perm.PERM_COMPLEX128
+    n = 28
+    A28 = inputs.complex_gaussian(n, seed=0)
+    d_a = torch.from_numpy(A28).cuda()
+    d_r = torch.zeros(2, dtype=torch.complex128, device="cuda")
+    ws = perm.device_buffer(perm.perm_ryser_workspace_bytes(C128, n))
+    perm.perm_ryser_async(n, d_a, n, d_r[0:1], ws)
+    torch.cuda.synchronize()
+    perm.perm_profile_enable(True)
+    perm.perm_profile_read()
+    for _ in range(10):
+        perm.perm_ryser_async(n, d_a, n, d_r[0:1], ws)
+    pr = perm.perm_profile_read()
+    perm.perm_profile_enable(False)
+    del ws
+    wsz = perm.device_buffer(perm.perm_workspace_bytes(C128, n))
+    perm.perm_solve_async(n, d_a, n, d_r[1:2], wsz)
+    torch.cuda.synchronize()
+    del wsz
+    r = d_r.cpu().numpy()
+    rms = pr.ryser_ms / max(1, pr.ryser_launches)
+    rflops = ryser_flops(n)
+    out["ryser_c128_n28"] = {"ms": round(rms, 4), "fp64_tflops": round(rflops / rms / 1e9, 3),
+                             "fp64_frac": round(rflops / rms / 1e9 / FP64_PEAK_TFLOPS, 4),
+                             "issue_bound_frac": round(ryser_issue_bound(n), 4),
+                             "rel_diff_vs_store_zechin": float(abs(r[0] - r[1]) / abs(r[1]))}
+    log(f"Ryser n=28: {rms:.3f} ms ({rflops / rms / 1e9:.1f} TFLOP/s), rel. diff. to Store-zechin "
+        f"{abs(r[0] - r[1]) / abs(r[1]):.2e}")
+
+
+def _extra_h2h(perm, inputs, out):
+    """Host-to-host n = 28 (PCIe-inclusive, for the record)."""
+    C128 = perm.PERM_COMPLEX128
     A28 = inputs.complex_gaussian(28, seed=0)
     ws = perm.device_buffer(perm.perm_workspace_bytes(C128, 28))
     perm.perm_solve(A28, workspace=ws)
@@ -208,7 +281,9 @@ def extras(perm, inputs, golden, np, torch, log):
     out["c128_n28_host_to_host_ms"] = round((time.perf_counter() - t0) * 200.0, 4)
     del ws
 
-    # 30x30 Bernoulli 0/1, exact (3 primes: 2 + 1 redundant)
+
+def _extra_int30(perm, inputs, golden, log, out):
+    """30x30 Bernoulli 0/1, exact (3 primes: 2 + 1 redundant)."""
     B = inputs.bernoulli01(30, seed=0)
     wsi = perm.device_buffer(perm.perm_workspace_bytes(perm.PERM_INT64, 30))
     v = perm.perm_solve(B, workspace=wsi)
@@ -224,7 +299,9 @@ def extras(perm, inputs, golden, np, torch, log):
     log(f"n=30 0/1 integer: {ms:.2f} ms")
     del wsi
 
-    # 10x10 uniform {0..9} integer, host to host
+
+def _extra_int10(perm, inputs, np, out):
+    """10x10 uniform {0..9} integer, host to host."""
     C = inputs.uniform_int(10, 0, 9, seed=0)
     wsc = perm.device_buffer(perm.perm_workspace_bytes(perm.PERM_INT64, 10))
     perm.perm_solve(C, workspace=wsc)
@@ -235,7 +312,10 @@ def extras(perm, inputs, golden, np, torch, log):
         ts.append(time.perf_counter() - t0)
     out["int_n10_us_median"] = round(float(np.median(ts)) * 1e6, 2)
 
-    # batched: 2^20 submatrices of a 64x64 Haar unitary, n uniform in 3..12
+
+def _extra_batch(perm, inputs, np, torch, log, out):
+    """Batched: 2^20 submatrices of a 64x64 Haar unitary, n uniform in 3..12."""
+    C128 = perm.PERM_COMPLEX128
     count = 1 << 20
     U = inputs.haar_unitary(64, seed=2018)
     t0 = time.perf_counter()
@@ -284,8 +364,6 @@ def extras(perm, inputs, golden, np, torch, log):
                          "launch": "graph replay of one persistent kernel"}
     log(f"batch 2^20: {med * 1000:.2f} ms ({count / med:.3e} perms/s); plain {plain_rate:.0f} perms/s")
     del d_mats, d_out, wsb
-    out["serving"] = serving(perm, inputs, np, torch, log)
-    return out
 
 
 def _percentiles(lat):
@@ -323,6 +401,11 @@ def _serve_trace(perm, srv, trace, log):
     return out
 
 
+WARMUP_REQ = 1000     # served first at each load, left out of the statistics
+MEASURED_REQ = 20000  # per load level (0.5, 0.8, 0.95 of saturation)
+SIDE_REQ = 10000      # the constrained-budget run and the plain FIFO baseline
+
+
 def serving(perm, inputs, np, torch, log):
     """Poisson arrivals of submatrix permanents of a 64x64 Haar unitary,
     n uniform in 5..12 with probability 0.8, else uniform in 20..28."""
@@ -339,10 +422,10 @@ def serving(perm, inputs, np, torch, log):
         sat = len(done) / (max(d[3] for d in done) - min(d[2] for d in done))
         log(f"serving saturation: {sat:.0f} requests/s ({time.perf_counter() - t0:.1f}s burst)")
         res["saturation_perms_per_s"] = round(sat, 1)
-        for frac in (0.5, 0.8):
+        for frac in (0.5, 0.8, 0.95):
             rate = frac * sat
-            trace = inputs.poisson_trace(U, 6000, rate, seed=11)
-            done = _serve_trace(perm, srv, trace, log)
+            trace = inputs.poisson_trace(U, WARMUP_REQ + MEASURED_REQ, rate, seed=11)
+            done = _serve_trace(perm, srv, trace, log)[WARMUP_REQ:]
             lat = [d[1] for d in done]
             span = max(d[3] for d in done) - min(d[2] for d in done)
             entry = {"offered_per_s": round(rate, 1), "perms_per_s": round(len(done) / span, 1)}
@@ -357,15 +440,15 @@ def serving(perm, inputs, np, torch, log):
     srv = perm.perm_server_create(pool, budget_bytes=8 << 30, max_large_slots=3, queue_capacity=100000,
                                   small_n_max=12, max_small_batch=4096)
     try:
-        trace = inputs.poisson_trace(U, 6000, 0.8 * sat, seed=11)
-        done = _serve_trace(perm, srv, trace, log)
-        entry = {"budget_bytes": 8 << 30}
+        trace = inputs.poisson_trace(U, WARMUP_REQ + SIDE_REQ, 0.8 * sat, seed=11)
+        done = _serve_trace(perm, srv, trace, log)[WARMUP_REQ:]
+        entry = {"budget_bytes": 8 << 30, "requests": len(done)}
         entry.update(_percentiles([d[1] for d in done]))
         res["load_0.8_budget_8GiB"] = entry
     finally:
         perm.perm_server_destroy(srv)
     # plain: the same trace served first-in first-out by perm_solve, one at a time
-    trace = inputs.poisson_trace(U, 6000, 0.8 * sat, seed=11)
+    trace = inputs.poisson_trace(U, WARMUP_REQ + SIDE_REQ, 0.8 * sat, seed=11)
     ws = perm.device_buffer(perm.perm_workspace_bytes(perm.PERM_COMPLEX128, 28))
     lat = []
     t0 = time.perf_counter()
@@ -375,8 +458,8 @@ def serving(perm, inputs, np, torch, log):
         perm.perm_solve(trace.mats[i], workspace=ws)
         lat.append(time.perf_counter() - t0 - trace.t_arrive[i])
     span = time.perf_counter() - t0
-    plain = {"perms_per_s": round(len(lat) / span, 1)}
-    plain.update(_percentiles(lat))
+    plain = {"perms_per_s": round(len(lat) / span, 1), "requests": len(lat) - WARMUP_REQ}
+    plain.update(_percentiles(lat[WARMUP_REQ:]))
     res["plain_fifo_perm_solve_load_0.8"] = plain
     log(f"plain FIFO: p50 {plain['p50_ms']} ms p99 {plain['p99_ms']} ms")
     return res

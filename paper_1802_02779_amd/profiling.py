@@ -22,6 +22,14 @@ def main():
     for name, calls, tot, avg, pct in cur.execute("select * from top_kernels"):
         short = re.sub(r"\(.*", "", name)
         print(f"| {short} | {calls} | {tot:.1f} | {avg:.3f} | {pct:.2f} |")
+    longest = list(cur.execute("select name, duration, grid_x, workgroup_x from kernels "
+                               "order by duration desc limit 8"))
+    if longest:
+        print("\nlongest dispatches:\n")
+        print("| kernel | us | workgroups | threads per workgroup |")
+        print("|---|---|---|---|")
+        for name, d, g, wg in longest:
+            print(f"| {re.sub(r'[(].*', '', name)} | {d / 1000:.1f} | {g // max(wg, 1)} | {wg} |")
     rows = list(cur.execute("select duration, grid_x, workgroup_x, lds_size from kernels "
                             "where name like '%k_layer_c128%' order by start"))
     if len(rows) >= n - 1:
