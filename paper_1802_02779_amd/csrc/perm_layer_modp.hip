@@ -145,12 +145,29 @@ __global__ __launch_bounds__(kLayerBlock) void k_layer_modp(const uint64_t *__re
     uint64_t *s_arow = smem_u + (size_t)RP * W;     // RP x t
     uint64_t *s_ha = s_arow + RP * t;               // RP x 32
     uint32_t *s_hb = (uint32_t *)(s_ha + RP * 32);  // 32
+    __shared__ uint32_t s_mact;
 
-    if (tid < ti.m) {
+    // high windows whose coefficient is nonzero for some prime, compacted
+    // (a zero residue contributes nothing, so dropping it is exact)
+    if (tid < 32) {
         int col = 0;
-        s_hb[tid] = high_window_base(ti.T, t, ti.kp, tid, &col);
+        const bool in = tid < ti.m;
+        const uint32_t hb = in ? high_window_base(ti.T, t, ti.kp, tid, &col) : 0u;
+        uint64_t a[RP];
+        bool nz = false;
 #pragma unroll
-        for (int r = 0; r < RP; r++) s_ha[r * 32 + tid] = red[(size_t)r * n * n + (size_t)(args.k - 1) * n + col];
+        for (int r = 0; r < RP; r++) {
+            a[r] = in ? red[(size_t)r * n * n + (size_t)(args.k - 1) * n + col] : 0u;
+            nz |= a[r] != 0;
+        }
+        const uint64_t act = __ballot(in && nz);  // lanes 0..31 of wave 0
+        if (in && nz) {
+            const int slot = __popcll(act & ((1ull << tid) - 1));
+            s_hb[slot] = hb;
+#pragma unroll
+            for (int r = 0; r < RP; r++) s_ha[r * 32 + slot] = a[r];
+        }
+        if (tid == 0) s_mact = (uint32_t)__popcll(act);
     }
     if (tid < t) {
 #pragma unroll
@@ -170,11 +187,32 @@ __global__ __launch_bounds__(kLayerBlock) void k_layer_modp(const uint64_t *__re
     for (int r = 0; r < RP; r++) pr[r] = primes[r];
     const uint32_t ck = ti.ck;
     const uint32_t *lt = g_lowtab + args.low_off[ti.g];
+    const int mact = (int)s_mact;
     for (uint32_t rr = tid; rr < ck; rr += kLayerBlock) {
         u128 acc[RP];
 #pragma unroll
         for (int r = 0; r < RP; r++) acc[r] = 0;
-        for (int p = 0; p < ti.kp; p++) {
+        // low columns: rank-table entries four at a time, then the LDS terms
+        int p = 0;
+        for (; p + 4 <= ti.kp; p += 4) {
+            uint32_t e[4];
+#pragma unroll
+            for (int u = 0; u < 4; u++) e[u] = lt[(uint32_t)(p + u) * ck + rr];
+#pragma unroll
+            for (int u = 0; u < 4; u++) {
+                const uint32_t idx = e[u] & 0xffffu, col = e[u] >> 16;
+                if (BIN) {
+                    if (s_arow[col] != 0) {
+#pragma unroll
+                        for (int r = 0; r < RP; r++) acc[r] += s_win[r * W + idx];
+                    }
+                } else {
+#pragma unroll
+                    for (int r = 0; r < RP; r++) acc[r] += (u128)s_arow[r * t + col] * s_win[r * W + idx];
+                }
+            }
+        }
+        for (; p < ti.kp; p++) {
             const uint32_t e = lt[(uint32_t)p * ck + rr];
             const uint32_t idx = e & 0xffffu, col = e >> 16;
             if (BIN) {
@@ -184,25 +222,29 @@ __global__ __launch_bounds__(kLayerBlock) void k_layer_modp(const uint64_t *__re
                 }
             } else {
 #pragma unroll
-                for (int r = 0; r < RP; r++) {
-                    const uint64_t a = s_arow[r * t + col];
-                    if (a != 0) acc[r] += (u128)a * s_win[r * W + idx];
-                }
+                for (int r = 0; r < RP; r++) acc[r] += (u128)s_arow[r * t + col] * s_win[r * W + idx];
             }
         }
-        for (int q = 0; q < ti.m; q++) {
-            const uint32_t base = s_hb[q] + rr;
-            if (BIN) {
-                if (s_ha[q] != 0) {
+        // active high windows, aligned with the tile: four windows' loads
+        // (all primes) in flight before they are added
+        int q = 0;
+        for (; q + 4 <= mact; q += 4) {
+            uint64_t w[4][RP];
 #pragma unroll
-                    for (int r = 0; r < RP; r++) acc[r] += prev[(size_t)r * plane + base];
-                }
-            } else {
+            for (int u = 0; u < 4; u++)
 #pragma unroll
-                for (int r = 0; r < RP; r++) {
-                    const uint64_t a = s_ha[r * 32 + q];
-                    if (a != 0) acc[r] += (u128)a * prev[(size_t)r * plane + base];
-                }
+                for (int r = 0; r < RP; r++) w[u][r] = prev[(size_t)r * plane + s_hb[q + u] + rr];
+#pragma unroll
+            for (int u = 0; u < 4; u++)
+#pragma unroll
+                for (int r = 0; r < RP; r++)
+                    acc[r] += BIN ? (u128)w[u][r] : (u128)s_ha[r * 32 + q + u] * w[u][r];
+        }
+        for (; q < mact; q++) {
+#pragma unroll
+            for (int r = 0; r < RP; r++) {
+                const uint64_t v = prev[(size_t)r * plane + s_hb[q] + rr];
+                acc[r] += BIN ? (u128)v : (u128)s_ha[r * 32 + q] * v;
             }
         }
 #pragma unroll
