@@ -137,14 +137,19 @@ int perm_solve_async(int n, const perm_c128_t *a_dev, int64_t lda, perm_c128_t *
  * computed row sums, summed in a fixed order.  O(n^2) memory, no tables; the
  * result is deterministic but, unlike perm_solve, not a Store-zechin chain:
  * inclusion-exclusion cancels, so it agrees with perm_solve only to within
- * the rounding bound derived for it (see the tests).  Complex128 only
- * (dt = PERM_INT64 returns PERM_EINVAL).
+ * the rounding bound derived for it (see the tests).  dt = PERM_INT64 gives
+ * the exact permanent (perm_int_t result) from the same walk on residues mod
+ * the 61-bit primes perm_solve uses (as many as the entry bound asks for,
+ * plus one redundant prime that must agree), recombined on the host.
  *
  * perm_ryser_workspace_bytes: device workspace needed for order n (0 for a
  * bad dtype or n outside 0..PERM_N_MAX).
- * perm_ryser: host matrix a (row-major, a[i*lda + j], perm_c128_t) -> host
- * *result; synchronizes the stream.  Errors as perm_solve.
- * perm_ryser_async: device matrix -> device *result_dev, stream-ordered.  */
+ * perm_ryser: host matrix a (row-major, a[i*lda + j]: perm_c128_t or
+ * int64_t) -> host *result (perm_c128_t or perm_int_t); synchronizes the
+ * stream.  Errors as perm_solve (PERM_EDEVICE also when the redundant prime
+ * disagrees).
+ * perm_ryser_async: complex128, device matrix -> device *result_dev,
+ * stream-ordered.  */
 size_t perm_ryser_workspace_bytes(perm_dtype_t dt, int n);
 int perm_ryser(perm_dtype_t dt, int n, const void *a, int64_t lda, void *result, void *workspace,
                size_t ws_bytes, void *stream);

@@ -872,6 +872,83 @@ static RyserLayout ryser_layout(int n) {
 
 size_t ryser_c128_workspace_bytes(int n) { return n < 1 ? 256 : ryser_layout(n).total; }
 
+// Integer layout: [residues, transposed, one n*n plane per prime][primes]
+// [partial sums per prime][residues of the result], room for PERM_MAX_PRIMES.
+struct RyserIntLayout {
+    size_t atr, primes, partial, res, total;
+};
+
+static RyserIntLayout ryser_int_layout(int n) {
+    RyserIntLayout L{};
+    L.atr = 0;
+    L.primes = align256((size_t)PERM_MAX_PRIMES * n * n * 8);
+    L.partial = L.primes + align256(PERM_MAX_PRIMES * 8);
+    L.res = L.partial + align256((size_t)PERM_MAX_PRIMES * ryser_blocks(n) * 8);
+    L.total = L.res + align256(PERM_MAX_PRIMES * 8);
+    return L;
+}
+
+size_t ryser_int_workspace_bytes(int n) { return n < 2 ? 256 : ryser_int_layout(n).total; }
+
+// Exact integer permanent by eq. (4): residues mod the primes the bound asks
+// for plus one redundant, Chinese remaindering on the host (as solve_int).
+static int ryser_int(int n, const int64_t *a, int64_t lda, perm_int_t *out, void *ws, size_t ws_bytes,
+                     hipStream_t s) {
+    if (n == 0) {
+        int_from_i64(1, out);
+        return PERM_OK;
+    }
+    if (n == 1) {
+        int_from_i64(a[0], out);
+        return PERM_OK;
+    }
+    const size_t need = ryser_int_workspace_bytes(n);
+    if (!ws || ws_bytes < need)
+        return set_error(PERM_ENOMEM, "workspace of %zu bytes < %zu needed for n=%d", ws_bytes, need, n);
+    int rc = prepare_device(s, nullptr);
+    if (rc) return rc;
+    const int R = primes_needed(n, a, lda);
+    const int Rt = R + 1;  // one redundant prime
+    if (Rt > PERM_MAX_PRIMES) return set_error(PERM_ERANGE, "needs %d primes (> %d)", Rt, PERM_MAX_PRIMES);
+    const auto &ps = primes61();
+    std::vector<uint64_t> atr((size_t)Rt * n * n);
+    for (int r = 0; r < Rt; r++) {
+        const uint64_t p = ps[r];
+        for (int i = 0; i < n; i++)
+            for (int j = 0; j < n; j++) {
+                const int64_t v = a[(int64_t)i * lda + j];
+                const uint64_t mag = v < 0 ? (uint64_t)0 - (uint64_t)v : (uint64_t)v;
+                uint64_t m = mag % p;
+                if (v < 0 && m != 0) m = p - m;
+                atr[(size_t)r * n * n + (size_t)j * n + i] = m;
+            }
+    }
+    const RyserIntLayout L = ryser_int_layout(n);
+    char *base = (char *)ws;
+    uint64_t *d_atr = (uint64_t *)(base + L.atr), *d_primes = (uint64_t *)(base + L.primes);
+    uint64_t *d_part = (uint64_t *)(base + L.partial), *d_res = (uint64_t *)(base + L.res);
+    HIPCALL(hipMemcpyAsync(d_atr, atr.data(), atr.size() * 8, hipMemcpyHostToDevice, s), "upload residues");
+    HIPCALL(hipMemcpyAsync(d_primes, ps.data(), Rt * 8, hipMemcpyHostToDevice, s), "upload primes");
+    hipEvent_t e0 = nullptr, e1 = nullptr;
+    const bool prof = profiling_on();
+    if (prof) {
+        e0 = profile_event();
+        e1 = profile_event();
+        if (e0) (void)hipEventRecord(e0, s);
+    }
+    const int hb = ryser_high_bits(n);
+    HIPCALL(launch_ryser_modp(d_atr, d_primes, Rt, n, n - hb, d_part, ryser_blocks(n), d_res, s),
+            "ryser modp kernel");
+    if (prof && e0 && e1) {
+        (void)hipEventRecord(e1, s);
+        profile_record(3, e0, e1);
+    }
+    std::vector<uint64_t> res(Rt);
+    HIPCALL(hipMemcpyAsync(res.data(), d_res, Rt * 8, hipMemcpyDeviceToHost, s), "download residues");
+    HIPCALL(hipStreamSynchronize(s), "hipStreamSynchronize");
+    return crt_to_int(res.data(), ps.data(), R, out);
+}
+
 // a_dev (device, lda) -> *result_dev (device), stream-ordered
 static int ryser_c128_device(int n, const void *a_dev, int64_t lda, void *result_dev, void *ws, size_t ws_bytes,
                              hipStream_t s) {
@@ -993,6 +1070,7 @@ int perm_solve_async(int n, const perm_c128_t *a_dev, int64_t lda, perm_c128_t *
 size_t perm_ryser_workspace_bytes(perm_dtype_t dt, int n) {
     if (n < 0 || n > PERM_N_MAX) return 0;
     if (dt == PERM_COMPLEX128) return ryser_c128_workspace_bytes(n);
+    if (dt == PERM_INT64) return ryser_int_workspace_bytes(n);
     return 0;
 }
 
@@ -1000,11 +1078,14 @@ int perm_ryser(perm_dtype_t dt, int n, const void *a, int64_t lda, void *result,
                size_t ws_bytes, void *stream) {
     try {
         t_err.clear();
-        if (dt != PERM_COMPLEX128) return set_error(PERM_EINVAL, "bad dtype %d for the Ryser path", (int)dt);
+        if (dt != PERM_COMPLEX128 && dt != PERM_INT64) return set_error(PERM_EINVAL, "bad dtype %d", (int)dt);
         if (n < 0) return set_error(PERM_EINVAL, "n = %d < 0", n);
         if (n > PERM_N_MAX) return set_error(PERM_ERANGE, "n = %d > %d", n, PERM_N_MAX);
         if (!result || (n > 0 && !a)) return set_error(PERM_EINVAL, "null pointer");
         if (n > 0 && lda < n) return set_error(PERM_EINVAL, "lda = %lld < n = %d", (long long)lda, n);
+        if (dt == PERM_INT64)
+            return ryser_int(n, (const int64_t *)a, lda, (perm_int_t *)result, workspace, ws_bytes,
+                             (hipStream_t)stream);
         perm_c128_t *out = (perm_c128_t *)result;
         if (n == 0) {
             out->re = 1.0;

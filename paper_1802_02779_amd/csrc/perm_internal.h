@@ -152,6 +152,11 @@ hipError_t launch_ryser_transpose_c128(const void *a_dev, int64_t lda, int n, vo
 // last may be partial); partial[blocks] sums, then *out = per(A) (device).
 hipError_t launch_ryser_c128(const void *at, int n, int m, void *partial, uint32_t blocks, void *out,
                              hipStream_t s);
+// Residues: atr[r*n*n + j*n + i] = a[i][j] mod primes[r] (device), for
+// r < nprimes; res[r] = per(A) mod primes[r] (device); partial holds
+// nprimes * blocks values.
+hipError_t launch_ryser_modp(const uint64_t *atr, const uint64_t *primes, int nprimes, int n, int m,
+                             uint64_t *partial, uint32_t blocks, uint64_t *res, hipStream_t s);
 hipError_t launch_batch_modp(const int64_t *mats, const int64_t *offsets, const uint32_t *order,
                              const BatchChunk *chunks, uint32_t nchunks, uint32_t *counter,
                              const uint64_t *primes, int nprimes, uint64_t *res, uint32_t count,

@@ -183,4 +183,129 @@ hipError_t launch_ryser_c128(const void *at, int n, int m, void *partial, uint32
     return hipGetLastError();
 }
 
+// ------------------------------------------------------------- mod p
+// The same walk on residues mod p = 2^61 - c (one prime per grid row):
+// row sums in [0, p), products folded with fold61, signed terms added mod p.
+
+__device__ __forceinline__ uint64_t ryser_addmod(uint64_t x, uint64_t y, uint64_t p) {
+    const uint64_t z = x + y;  // < 2^62
+    return z >= p ? z - p : z;
+}
+
+__device__ __forceinline__ uint64_t ryser_mulmod(uint64_t x, uint64_t y, uint64_t p) {
+    return fold61((u128)x * y, p);
+}
+
+template <int N>
+__device__ __forceinline__ uint64_t ryser_product_modp(const uint64_t *r, uint64_t p) {
+    constexpr int L = N < 4 ? N : 4;
+    uint64_t c[L];
+#pragma unroll
+    for (int k = 0; k < L; k++) c[k] = r[k];
+#pragma unroll
+    for (int i = L; i < N; i++) c[i % L] = ryser_mulmod(c[i % L], r[i], p);
+#pragma unroll
+    for (int k = 1; k < L; k++) c[0] = ryser_mulmod(c[0], c[k], p);
+    return c[0];
+}
+
+__device__ __forceinline__ uint64_t ryser_block_sum_modp(uint64_t v, uint64_t p, uint64_t *s) {
+    s[threadIdx.x] = v;
+    __syncthreads();
+    for (int w = kRyserBlock / 2; w > 0; w >>= 1) {
+        if ((int)threadIdx.x < w) s[threadIdx.x] = ryser_addmod(s[threadIdx.x], s[threadIdx.x + w], p);
+        __syncthreads();
+    }
+    return s[0];
+}
+
+// atr: prime r's transposed residues at atr[r*n*n + j*n + i]; partial[r*gridDim.x + block]
+template <int N>
+__global__ __launch_bounds__(kRyserBlock) void k_ryser_modp(const uint64_t *__restrict__ atr,
+                                                           const uint64_t *__restrict__ primes, int m,
+                                                           uint32_t nthreads, uint64_t *__restrict__ partial) {
+    __shared__ uint64_t red[kRyserBlock];
+    const uint64_t p = primes[blockIdx.y];
+    const uint64_t *at = atr + (size_t)blockIdx.y * N * N;
+    const uint32_t g = blockIdx.x * kRyserBlock + threadIdx.x;
+    uint64_t acc = 0;
+    if (g < nthreads) {
+        const uint32_t x0 = g << m;
+        uint32_t S = x0 ^ (x0 >> 1);
+        uint64_t r[N];
+#pragma unroll
+        for (int i = 0; i < N; i++) r[i] = 0;
+        for (int j = 0; j < N; j++) {
+            if ((S >> j) & 1u) {
+                const uint64_t *col = at + (size_t)j * N;
+#pragma unroll
+                for (int i = 0; i < N; i++) r[i] = ryser_addmod(r[i], col[i], p);
+            }
+        }
+        bool neg = __builtin_popcount(S) & 1;
+        uint64_t pr = ryser_product_modp<N>(r, p);
+        acc = neg ? (pr ? p - pr : 0) : pr;
+        const uint32_t steps = 1u << m;
+        for (uint32_t t = 1; t < steps; t++) {
+            const int j = __builtin_ctz(t);
+            S ^= 1u << j;
+            const bool add = (S >> j) & 1u;
+            const uint64_t *col = at + (size_t)j * N;
+#pragma unroll
+            for (int i = 0; i < N; i++) {
+                const uint64_t a = col[i];
+                r[i] = ryser_addmod(r[i], add ? a : (a ? p - a : 0), p);
+            }
+            neg = !neg;
+            pr = ryser_product_modp<N>(r, p);
+            acc = ryser_addmod(acc, neg ? (pr ? p - pr : 0) : pr, p);
+        }
+    }
+    const uint64_t tot = ryser_block_sum_modp(acc, p, red);
+    if (threadIdx.x == 0) partial[(size_t)blockIdx.y * gridDim.x + blockIdx.x] = tot;
+}
+
+// res[r] = (-1)^n * (sum of prime r's partial sums) mod p_r, fixed order
+__global__ __launch_bounds__(kRyserBlock) void k_ryser_final_modp(const uint64_t *__restrict__ partial, uint32_t np,
+                                                                 const uint64_t *__restrict__ primes, int n,
+                                                                 uint64_t *__restrict__ res) {
+    __shared__ uint64_t red[kRyserBlock];
+    const uint64_t p = primes[blockIdx.x];
+    const uint64_t *pp = partial + (size_t)blockIdx.x * np;
+    uint64_t s = 0;
+    for (uint32_t k = threadIdx.x; k < np; k += kRyserBlock) s = ryser_addmod(s, pp[k], p);
+    const uint64_t tot = ryser_block_sum_modp(s, p, red);
+    if (threadIdx.x == 0) res[blockIdx.x] = (n & 1) ? (tot ? p - tot : 0) : tot;
+}
+
+template <int N>
+static hipError_t launch_ryser_modp_n(const uint64_t *atr, const uint64_t *primes, int nprimes, int m,
+                                      uint32_t nthreads, uint32_t blocks, uint64_t *partial, hipStream_t s) {
+    hipLaunchKernelGGL(k_ryser_modp<N>, dim3(blocks, nprimes), dim3(kRyserBlock), 0, s, atr, primes, m, nthreads,
+                       partial);
+    return hipGetLastError();
+}
+
+hipError_t launch_ryser_modp(const uint64_t *atr, const uint64_t *primes, int nprimes, int n, int m,
+                             uint64_t *partial, uint32_t blocks, uint64_t *res, hipStream_t s) {
+    const uint32_t nthreads = 1u << (n - m);
+    hipError_t e = hipErrorInvalidValue;
+    switch (n) {
+#define PERM_RYSER_CASE(K) \
+    case K: e = launch_ryser_modp_n<K>(atr, primes, nprimes, m, nthreads, blocks, partial, s); break;
+        PERM_RYSER_CASE(1) PERM_RYSER_CASE(2) PERM_RYSER_CASE(3) PERM_RYSER_CASE(4) PERM_RYSER_CASE(5)
+        PERM_RYSER_CASE(6) PERM_RYSER_CASE(7) PERM_RYSER_CASE(8) PERM_RYSER_CASE(9) PERM_RYSER_CASE(10)
+        PERM_RYSER_CASE(11) PERM_RYSER_CASE(12) PERM_RYSER_CASE(13) PERM_RYSER_CASE(14) PERM_RYSER_CASE(15)
+        PERM_RYSER_CASE(16) PERM_RYSER_CASE(17) PERM_RYSER_CASE(18) PERM_RYSER_CASE(19) PERM_RYSER_CASE(20)
+        PERM_RYSER_CASE(21) PERM_RYSER_CASE(22) PERM_RYSER_CASE(23) PERM_RYSER_CASE(24) PERM_RYSER_CASE(25)
+        PERM_RYSER_CASE(26) PERM_RYSER_CASE(27) PERM_RYSER_CASE(28) PERM_RYSER_CASE(29) PERM_RYSER_CASE(30)
+#undef PERM_RYSER_CASE
+    default: return hipErrorInvalidValue;
+    }
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL(k_ryser_final_modp, dim3(nprimes), dim3(kRyserBlock), 0, s, (const uint64_t *)partial, blocks,
+                       primes, n, res);
+    return hipGetLastError();
+}
+
 }  // namespace permgpu

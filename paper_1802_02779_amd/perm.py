@@ -256,19 +256,27 @@ def perm_ryser_workspace_bytes(dtype: int, n: int) -> int:
     return int(lib().perm_ryser_workspace_bytes(dtype, n))
 
 
-def perm_ryser(A, workspace=None, stream=None) -> complex:
-    """per(A) of a host complex128 matrix by Ryser's formula (eq. 4)."""
-    A = np.ascontiguousarray(np.asarray(A), dtype=np.complex128)
+def perm_ryser(A, workspace=None, stream=None):
+    """per(A) of a host matrix by Ryser's formula (eq. 4): complex128 ->
+    complex, int64 -> exact Python int."""
+    A = np.asarray(A)
+    dt = _dtype_of(A)
+    A = np.ascontiguousarray(A, dtype=np.int64 if dt == PERM_INT64 else np.complex128)
     if A.ndim != 2 or A.shape[0] != A.shape[1]:
         raise ValueError("square matrix expected")
     n = A.shape[0]
-    need = perm_ryser_workspace_bytes(PERM_COMPLEX128, n)
+    need = perm_ryser_workspace_bytes(dt, n)
     ws = workspace if workspace is not None else (device_buffer(need) if n >= 1 else None)
     ws_ptr = ws.data_ptr() if ws is not None else None
     ws_bytes = ws.numel() * ws.element_size() if ws is not None else 0
     s = _stream_ptr(stream) if n >= 1 else None
+    if dt == PERM_INT64:
+        out = perm_int_t()
+        _check(lib().perm_ryser(dt, n, A.ctypes.data if n else None, max(n, 1), ctypes.byref(out),
+                                ws_ptr, ws_bytes, s))
+        return out.value()
     out = perm_c128_t()
-    _check(lib().perm_ryser(PERM_COMPLEX128, n, A.ctypes.data if n else None, max(n, 1), ctypes.byref(out),
+    _check(lib().perm_ryser(dt, n, A.ctypes.data if n else None, max(n, 1), ctypes.byref(out),
                             ws_ptr, ws_bytes, s))
     return complex(out.re, out.im)
 

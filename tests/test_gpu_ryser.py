@@ -1,7 +1,9 @@
 """GPU parity of the Ryser path (eq. 4): perm_ryser / perm_ryser_async.
 
+Integer matrices are exact (residues mod 61-bit primes, Chinese
+remaindering): bit-exact against the exact permanent and the stored values.
 Inclusion-exclusion cancels, so Ryser in fp64 is not bitwise equal to the
-Store-zechin chain.  Two kinds of check:
+Store-zechin chain.  Two kinds of check for complex128:
   * inputs whose every intermediate is an integer below 2^53 (entries in
     {-1, 0, 1} + i{-1, 0, 1}, n <= 10): fp64 is exact, so the result must
     equal the exact permanent bit for bit;
@@ -94,8 +96,10 @@ def test_ryser_trivial_orders_and_errors(P):
     assert P.perm_ryser(np.zeros((0, 0), dtype=np.complex128)) == 1
     a = np.array([[2.5 - 1.25j]])
     assert bits(P.perm_ryser(a)) == bits(2.5 - 1.25j)
-    assert P.perm_ryser_workspace_bytes(P.PERM_INT64, 5) == 0
+    assert P.perm_ryser_workspace_bytes(P.PERM_INT64, 5) > 0
     assert P.perm_ryser_workspace_bytes(P.PERM_COMPLEX128, 31) == 0
+    assert P.perm_ryser(np.zeros((0, 0), dtype=np.int64)) == 1
+    assert P.perm_ryser(np.array([[-7]], dtype=np.int64)) == -7
     small = P.device_buffer(16)
     with pytest.raises(P.PermError) as e:
         P.perm_ryser(inputs.complex_gaussian(10, seed=1), workspace=small)
@@ -113,3 +117,47 @@ def test_ryser_full_size_agrees_with_store_zechin(P, golden_dir, key, n, seed):
     rel = abs(got - ref) / abs(ref)
     print(f"[gpu] ryser n={n} relative difference to Store-zechin {rel:.3e}", flush=True)
     assert rel < 1e-6
+
+
+# ------------------------------------------------------------------ int64
+def test_ryser_int_random_exact(P):
+    rng = np.random.default_rng(80)
+    for n in range(2, 13):
+        A = rng.integers(-9, 10, size=(n, n), dtype=np.int64)
+        print(f"[gpu] ryser int n={n}", flush=True)
+        ref = exact.per_definition(A.tolist()) if n <= 7 else native.per_int(A)
+        assert P.perm_ryser(A) == ref, n
+
+
+def test_ryser_int_extreme_entries(P):
+    rng = np.random.default_rng(81)
+    for n in (2, 3, 5, 8):
+        A = rng.integers(-(2 ** 63), 2 ** 63 - 1, size=(n, n), dtype=np.int64, endpoint=True)
+        A[0, 0] = -(2 ** 63)
+        print(f"[gpu] ryser int extreme n={n}", flush=True)
+        assert P.perm_ryser(A) == exact.per_store_zechin(exact.as_exact_matrix(A)), n
+
+
+def test_ryser_int_stored_n10(P, golden_dir):
+    cfg = json.load(open(os.path.join(golden_dir, "large_configs.json")))
+    for s in range(4):
+        A = inputs.uniform_int(10, 0, 9, seed=s)
+        assert str(P.perm_ryser(A)) == cfg[f"int_n10_u09_s{s}"]["value"], s
+
+
+def test_ryser_int_closed_forms(P):
+    n = 20
+    assert P.perm_ryser(np.ones((n, n), dtype=np.int64)) == math.factorial(n)
+    assert P.perm_ryser(np.eye(n, dtype=np.int64)) == 1
+    d = [1, 0]
+    for k in range(2, n + 1):
+        d.append((k - 1) * (d[-1] + d[-2]))
+    assert P.perm_ryser(np.ones((n, n), dtype=np.int64) - np.eye(n, dtype=np.int64)) == d[n]
+
+
+def test_ryser_int_n30_bernoulli_equals_store_zechin(P, golden_dir):
+    """Two independent exact GPU algorithms on the 30x30 0/1 workload."""
+    cfg = json.load(open(os.path.join(golden_dir, "large_configs.json")))["int_n30_bern_s0"]
+    B = inputs.bernoulli01(30, seed=0)
+    print("[gpu] ryser int n=30", flush=True)
+    assert str(P.perm_ryser(B)) == cfg["value"]
