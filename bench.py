@@ -85,7 +85,8 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-extras", action="store_true")
     ap.add_argument("--only", default="",
-                    help="comma list of extra sections to run (n26, ryser, h2h, int30, int10, batch, serving); "
+                    help="comma list of extra sections to run (n26, ryser, n34, h2h, int30, int10, batch, "
+                         "serving); "
                          "default: all")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="first copy 1 GiB device to device (a plain copy kernel of known size, "
@@ -202,6 +203,8 @@ def extras(perm, inputs, golden, np, torch, log, only=frozenset()):
         _extra_n26(perm, inputs, golden, torch, log, out)
     if want("ryser"):
         _extra_ryser(perm, inputs, torch, log, out)
+    if want("n34"):
+        _extra_n34(perm, inputs, torch, log, out)
     if want("h2h"):
         _extra_h2h(perm, inputs, out)
     if want("int30"):
@@ -276,6 +279,41 @@ def _extra_ryser(perm, inputs, torch, log, out):
                              "rel_diff_vs_store_zechin": float(abs(r[0] - r[1]) / abs(r[1]))}
     log(f"Ryser n=28: {rms:.3f} ms ({rflops / rms / 1e9:.1f} TFLOP/s), rel. diff. to Store-zechin "
         f"{abs(r[0] - r[1]) / abs(r[1]):.2e}")
+
+
+def _extra_n34(perm, inputs, torch, log, out):
+    """The largest order: Store-zechin sweep (75 GB of layer tables) and
+    Ryser's formula on the same 34x34 complex Gaussian matrix."""
+    C128 = perm.PERM_COMPLEX128
+    n = 34
+    A = inputs.complex_gaussian(n, seed=n)
+    d_a = torch.from_numpy(A).cuda()
+    d_r = torch.zeros(2, dtype=torch.complex128, device="cuda")
+    ws = perm.device_buffer(perm.perm_workspace_bytes(C128, n))
+    perm.perm_solve_async(n, d_a, n, d_r[0:1], ws)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(3):
+        perm.perm_solve_async(n, d_a, n, d_r[0:1], ws)
+    torch.cuda.synchronize()
+    sz_ms = (time.perf_counter() - t0) * 1000.0 / 3
+    ws_gb = ws.numel() / 1e9
+    del ws
+    torch.cuda.empty_cache()
+    wr = perm.device_buffer(perm.perm_ryser_workspace_bytes(C128, n))
+    perm.perm_ryser_async(n, d_a, n, d_r[1:2], wr)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    perm.perm_ryser_async(n, d_a, n, d_r[1:2], wr)
+    torch.cuda.synchronize()
+    ry_ms = (time.perf_counter() - t0) * 1000.0
+    r = d_r.cpu().numpy()
+    out["c128_n34"] = {"store_zechin_ms": round(sz_ms, 2), "workspace_gb": round(ws_gb, 1),
+                       "roofline_ms_hbm": round(layer_bytes(n) / HBM_PEAK_GBS / 1e6, 2),
+                       "ryser_ms": round(ry_ms, 2),
+                       "ryser_fp64_frac": round(ryser_flops(n) / ry_ms / 1e9 / FP64_PEAK_TFLOPS, 4),
+                       "rel_diff": float(abs(r[1] - r[0]) / abs(r[0]))}
+    log(f"n=34 complex: Store-zechin {sz_ms:.1f} ms ({ws_gb:.0f} GB), Ryser {ry_ms:.1f} ms")
 
 
 def _extra_h2h(perm, inputs, out):

@@ -45,9 +45,9 @@
 extern "C" {
 #endif
 
-#define PERM_N_MAX 30        /* largest order accepted by perm_solve */
+#define PERM_N_MAX 34        /* largest order accepted by perm_solve (colex ranks stay below 2^32) */
 #define PERM_BATCH_N_MAX 12  /* largest order accepted by perm_solve_batch */
-#define PERM_INT_LIMBS 32    /* 2048-bit magnitude: enough for any int64 input at n = 30 */
+#define PERM_INT_LIMBS 36    /* 2304-bit magnitude: enough for any int64 input at n = 34 */
 #define PERM_MAX_PRIMES 40   /* primes the integer path may use */
 
 typedef enum { PERM_INT64 = 0, PERM_COMPLEX128 = 1 } perm_dtype_t;

@@ -1214,6 +1214,8 @@ int perm_tuning_key(char *buf, size_t len) {
     return PERM_OK;
 }
 
+// Reads up to `count` integers of the array `name`; a shorter array (a file
+// written when fewer orders existed) leaves the remaining entries unchanged.
 static bool json_int_array(const std::string &s, const char *name, int *out, int count) {
     const std::string pat = std::string("\"") + name + "\"";
     size_t p = s.find(pat);
@@ -1221,7 +1223,8 @@ static bool json_int_array(const std::string &s, const char *name, int *out, int
     p = s.find('[', p);
     if (p == std::string::npos) return false;
     const char *c = s.c_str() + p + 1;
-    for (int i = 0; i < count; i++) {
+    while (*c == ' ' || *c == '\n' || *c == '\t') c++;
+    for (int i = 0; i < count && *c != ']'; i++) {
         char *end = nullptr;
         long v = std::strtol(c, &end, 10);
         if (end == c) return false;
@@ -1229,7 +1232,7 @@ static bool json_int_array(const std::string &s, const char *name, int *out, int
         c = end;
         while (*c == ' ' || *c == ',' || *c == '\n' || *c == '\t') c++;
     }
-    return true;
+    return *c == ']';
 }
 
 int perm_tuning_load(const char *path) {

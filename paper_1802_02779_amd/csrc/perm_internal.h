@@ -23,22 +23,24 @@
 
 namespace permgpu {
 
-constexpr int kNMax = 30;
+constexpr int kNMax = 34;
 constexpr int kTMax = 15;        // largest low window (columns) of a tile
-constexpr int kHighBits = 17;    // largest high part (columns) of a tile
+constexpr int kHighBits = 19;    // largest high part (columns) of a tile (n - t at n = 34, t = 15)
 constexpr int kBatchNMax = 12;   // largest order of the on-chip batched kernel
 constexpr int kRPMax = 3;        // primes that share one integer sweep
 constexpr int kMaxGroups = 32;   // k' groups in one layer launch
 constexpr int kBatchBlockComplex = 512;  // threads of a complex batched workgroup
 constexpr int kBatchBlockInt = 256;      // threads of an integer batched workgroup
 
+constexpr int kBinomDim = kNMax + 1;  // C(i, j) for 0 <= i, j <= kNMax (all below 2^32)
+
 struct BinomTable {
-    uint32_t v[33][33];
+    uint32_t v[kBinomDim][kBinomDim];
 };
 
 constexpr BinomTable make_binom() {
     BinomTable b{};
-    for (int i = 0; i <= 32; i++) {
+    for (int i = 0; i <= kNMax; i++) {
         b.v[i][0] = 1;
         for (int j = 1; j <= i; j++)
             b.v[i][j] = b.v[i - 1][j - 1] + (j <= i - 1 ? b.v[i - 1][j] : 0u);
@@ -48,8 +50,14 @@ constexpr BinomTable make_binom() {
 
 inline constexpr BinomTable kBinom = make_binom();
 
+// LDS copies of the binomial table (per-thread paths): words rounded up to a
+// 16-byte multiple so that what follows is aligned; slots for one row of A.
+constexpr int kBinomWords = (kBinomDim * kBinomDim + 3) & ~3;
+constexpr int kRowSlots = 36;  // >= kNMax
+static_assert(kRowSlots >= kNMax, "row slots");
+
 constexpr uint32_t binom_host(int i, int j) {
-    return (i < 0 || j < 0 || i > 32 || j > 32) ? 0u : kBinom.v[i][j];
+    return (i < 0 || j < 0 || i > kNMax || j > kNMax) ? 0u : kBinom.v[i][j];
 }
 
 // lowtab layout: for each t in 1..kTMax, for each k' in 1..t, entries

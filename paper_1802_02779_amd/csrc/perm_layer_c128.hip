@@ -40,10 +40,10 @@ hipError_t launch_pack_c128(const void *a_dev, int64_t lda, int n, void *packed,
 // the aligned windows (neighbouring threads read neighbouring entries).
 __device__ void layer_c128_thin(const double2 *__restrict__ prev, double2 *__restrict__ next,
                                 const double2 *__restrict__ A, const LayerArgs &args, double2 *smem) {
-    uint32_t *s_bin = (uint32_t *)smem;               // C(i, j) at [i * 33 + j]
-    double2 *s_arow = (double2 *)(s_bin + 33 * 33);   // row k-1 of A
+    uint32_t *s_bin = (uint32_t *)smem;                  // C(i, j) at [i * kBinomDim + j]
+    double2 *s_arow = (double2 *)(s_bin + kBinomWords);  // row k-1 of A
     const int tid = threadIdx.x;
-    for (int i = tid; i < 33 * 33; i += kLayerBlock) s_bin[i] = c_binom.v[i / 33][i % 33];
+    for (int i = tid; i < kBinomDim * kBinomDim; i += kLayerBlock) s_bin[i] = c_binom.v[i / kBinomDim][i % kBinomDim];
     if (tid < args.n) s_arow[tid] = A[(size_t)(args.k - 1) * args.n + tid];
     __syncthreads();
     const uint32_t gid = (blockIdx.x - args.big_blocks) * kLayerBlock + tid;
@@ -61,9 +61,9 @@ __device__ void layer_c128_thin(const double2 *__restrict__ prev, double2 *__res
         for (int i = 1; b; i++) {
             const int h = __ffs(b) - 1 + t;
             b &= b - 1;
-            base_out += s_bin[h * 33 + kp + i];
-            base_low += s_bin[h * 33 + kp + i - 1];
-            if (i >= 2) base_h += s_bin[h * 33 + kp + i - 1];
+            base_out += s_bin[h * kBinomDim + kp + i];
+            base_low += s_bin[h * kBinomDim + kp + i - 1];
+            if (i >= 2) base_h += s_bin[h * kBinomDim + kp + i - 1];
         }
     }
     double re = 0.0, im = 0.0;
@@ -79,7 +79,7 @@ __device__ void layer_c128_thin(const double2 *__restrict__ prev, double2 *__res
     while (b) {
         const int h = __ffs(b) - 1 + t;
         b &= b - 1;
-        if (q > 1) base_h = base_h + s_bin[hprev * 33 + kp + q - 1] - s_bin[h * 33 + kp + q - 1];
+        if (q > 1) base_h = base_h + s_bin[hprev * kBinomDim + kp + q - 1] - s_bin[h * kBinomDim + kp + q - 1];
         cfma(re, im, s_arow[h], prev[base_h + r]);
         hprev = h;
         q++;

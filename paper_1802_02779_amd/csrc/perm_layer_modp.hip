@@ -49,13 +49,13 @@ template <int RP, bool BIN>
 __device__ void layer_modp_thin(const uint64_t *__restrict__ prev, uint64_t *__restrict__ next, size_t plane,
                                 const uint64_t *__restrict__ red, const uint64_t *__restrict__ primes,
                                 const LayerArgs &args, uint64_t *smem) {
-    uint32_t *s_bin = (uint32_t *)smem;                 // C(i, j) at [i * 33 + j]
-    uint64_t *s_arow = (uint64_t *)(s_bin + 33 * 33 + 1);  // RP x 32 residues of row k-1 (8-byte aligned)
+    uint32_t *s_bin = (uint32_t *)smem;                 // C(i, j) at [i * kBinomDim + j]
+    uint64_t *s_arow = (uint64_t *)(s_bin + kBinomWords);  // RP x kRowSlots residues of row k-1
     const int tid = threadIdx.x, n = args.n;
-    for (int i = tid; i < 33 * 33; i += kLayerBlock) s_bin[i] = c_binom.v[i / 33][i % 33];
+    for (int i = tid; i < kBinomDim * kBinomDim; i += kLayerBlock) s_bin[i] = c_binom.v[i / kBinomDim][i % kBinomDim];
     if (tid < n) {
 #pragma unroll
-        for (int r = 0; r < RP; r++) s_arow[r * 32 + tid] = red[(size_t)r * n * n + (size_t)(args.k - 1) * n + tid];
+        for (int r = 0; r < RP; r++) s_arow[r * kRowSlots + tid] = red[(size_t)r * n * n + (size_t)(args.k - 1) * n + tid];
     }
     __syncthreads();
     const uint32_t gid = (blockIdx.x - args.big_blocks) * kLayerBlock + tid;
@@ -72,9 +72,9 @@ __device__ void layer_modp_thin(const uint64_t *__restrict__ prev, uint64_t *__r
         for (int i = 1; b; i++) {
             const int h = __ffs(b) - 1 + t;
             b &= b - 1;
-            base_out += s_bin[h * 33 + kp + i];
-            base_low += s_bin[h * 33 + kp + i - 1];
-            if (i >= 2) base_h += s_bin[h * 33 + kp + i - 1];
+            base_out += s_bin[h * kBinomDim + kp + i];
+            base_low += s_bin[h * kBinomDim + kp + i - 1];
+            if (i >= 2) base_h += s_bin[h * kBinomDim + kp + i - 1];
         }
     }
     u128 acc[RP];
@@ -92,7 +92,7 @@ __device__ void layer_modp_thin(const uint64_t *__restrict__ prev, uint64_t *__r
         } else {
 #pragma unroll
             for (int r = 0; r < RP; r++) {
-                const uint64_t a = s_arow[r * 32 + col];
+                const uint64_t a = s_arow[r * kRowSlots + col];
                 if (a != 0) acc[r] += (u128)a * prev[(size_t)r * plane + idx];
             }
         }
@@ -102,7 +102,7 @@ __device__ void layer_modp_thin(const uint64_t *__restrict__ prev, uint64_t *__r
     while (b) {
         const int h = __ffs(b) - 1 + t;
         b &= b - 1;
-        if (q > 1) base_h = base_h + s_bin[hprev * 33 + kp + q - 1] - s_bin[h * 33 + kp + q - 1];
+        if (q > 1) base_h = base_h + s_bin[hprev * kBinomDim + kp + q - 1] - s_bin[h * kBinomDim + kp + q - 1];
         const uint32_t idx = base_h + rr;
         if (BIN) {
             if (s_arow[h] != 0) {
@@ -112,7 +112,7 @@ __device__ void layer_modp_thin(const uint64_t *__restrict__ prev, uint64_t *__r
         } else {
 #pragma unroll
             for (int r = 0; r < RP; r++) {
-                const uint64_t a = s_arow[r * 32 + h];
+                const uint64_t a = s_arow[r * kRowSlots + h];
                 if (a != 0) acc[r] += (u128)a * prev[(size_t)r * plane + idx];
             }
         }

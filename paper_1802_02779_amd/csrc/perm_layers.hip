@@ -133,13 +133,13 @@ uint32_t plan_layer(int n, int k, int t, int chunk, int nt_store, uint32_t thin_
 
 size_t layer_lds_bytes_c128(const LayerArgs &a) {
     const size_t tiled = (size_t)(a.lds_window + a.t + 32) * 16 + 32 * 4;
-    const size_t thin = 33 * 33 * 4 + 32 * 16;
+    const size_t thin = (size_t)kBinomWords * 4 + kRowSlots * 16;
     return tiled > thin ? tiled : thin;
 }
 
 size_t layer_lds_bytes_modp(const LayerArgs &a, int rp) {
     const size_t tiled = (size_t)rp * (a.lds_window + a.t + 32) * 8 + 32 * 4;
-    const size_t thin = (33 * 33 + 1) * 4 + (size_t)rp * 32 * 8;
+    const size_t thin = (size_t)kBinomWords * 4 + (size_t)rp * kRowSlots * 8;
     return tiled > thin ? tiled : thin;
 }
 

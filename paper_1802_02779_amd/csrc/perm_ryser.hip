@@ -5,7 +5,8 @@
 //   per(A) = (-1)^n * sum over column subsets S of (-1)^|S| * prod_i r_i(S),
 //   r_i(S) = sum_{j in S} a[i][j].
 //
-// Subsets are visited in binary-reflected Gray-code order: x = 0 .. 2^n - 1,
+// Subsets are visited in binary-reflected Gray-code order: x = 0 .. 2^n - 1
+// (64-bit codes),
 // S(x) = x ^ (x >> 1), so consecutive subsets differ in column ctz(x) and
 // the row sums change by one column.  Thread g owns the 2^m consecutive
 // codes x = g*2^m + t (t < 2^m); for t > 0 the changed column is ctz(t) for
@@ -93,8 +94,8 @@ __global__ __launch_bounds__(kRyserBlock) void k_ryser_c128(const double2 *__res
     const uint32_t g = blockIdx.x * kRyserBlock + threadIdx.x;
     double accr = 0.0, acci = 0.0;
     if (g < nthreads) {
-        const uint32_t x0 = g << m;
-        uint32_t S = x0 ^ (x0 >> 1);
+        const uint64_t x0 = (uint64_t)g << m;
+        uint64_t S = x0 ^ (x0 >> 1);
         double rr[N], ri[N];
 #pragma unroll
         for (int i = 0; i < N; i++) rr[i] = ri[i] = 0.0;
@@ -109,7 +110,7 @@ __global__ __launch_bounds__(kRyserBlock) void k_ryser_c128(const double2 *__res
                 }
             }
         }
-        double sg = (__builtin_popcount(S) & 1) ? -1.0 : 1.0;
+        double sg = (__builtin_popcountll(S) & 1) ? -1.0 : 1.0;
         double pr, pi;
         ryser_product<N>(rr, ri, pr, pi);
         accr = sg * pr;
@@ -118,7 +119,7 @@ __global__ __launch_bounds__(kRyserBlock) void k_ryser_c128(const double2 *__res
         for (uint32_t t = 1; t < steps; t++) {
             // next code: column j = ctz(t) enters or leaves S
             const int j = __builtin_ctz(t);
-            S ^= 1u << j;
+            S ^= 1ull << j;
             const double s = ((S >> j) & 1u) ? 1.0 : -1.0;
             const double2 *col = at + (size_t)j * N;
 #pragma unroll
@@ -174,6 +175,7 @@ hipError_t launch_ryser_c128(const void *at, int n, int m, void *partial, uint32
         PERM_RYSER_CASE(16) PERM_RYSER_CASE(17) PERM_RYSER_CASE(18) PERM_RYSER_CASE(19) PERM_RYSER_CASE(20)
         PERM_RYSER_CASE(21) PERM_RYSER_CASE(22) PERM_RYSER_CASE(23) PERM_RYSER_CASE(24) PERM_RYSER_CASE(25)
         PERM_RYSER_CASE(26) PERM_RYSER_CASE(27) PERM_RYSER_CASE(28) PERM_RYSER_CASE(29) PERM_RYSER_CASE(30)
+        PERM_RYSER_CASE(31) PERM_RYSER_CASE(32) PERM_RYSER_CASE(33) PERM_RYSER_CASE(34)
 #undef PERM_RYSER_CASE
     default: return hipErrorInvalidValue;
     }
@@ -230,8 +232,8 @@ __global__ __launch_bounds__(kRyserBlock) void k_ryser_modp(const uint64_t *__re
     const uint32_t g = blockIdx.x * kRyserBlock + threadIdx.x;
     uint64_t acc = 0;
     if (g < nthreads) {
-        const uint32_t x0 = g << m;
-        uint32_t S = x0 ^ (x0 >> 1);
+        const uint64_t x0 = (uint64_t)g << m;
+        uint64_t S = x0 ^ (x0 >> 1);
         uint64_t r[N];
 #pragma unroll
         for (int i = 0; i < N; i++) r[i] = 0;
@@ -242,13 +244,13 @@ __global__ __launch_bounds__(kRyserBlock) void k_ryser_modp(const uint64_t *__re
                 for (int i = 0; i < N; i++) r[i] = ryser_addmod(r[i], col[i], p);
             }
         }
-        bool neg = __builtin_popcount(S) & 1;
+        bool neg = __builtin_popcountll(S) & 1;
         uint64_t pr = ryser_product_modp<N>(r, p);
         acc = neg ? (pr ? p - pr : 0) : pr;
         const uint32_t steps = 1u << m;
         for (uint32_t t = 1; t < steps; t++) {
             const int j = __builtin_ctz(t);
-            S ^= 1u << j;
+            S ^= 1ull << j;
             const bool add = (S >> j) & 1u;
             const uint64_t *col = at + (size_t)j * N;
 #pragma unroll
@@ -299,6 +301,7 @@ hipError_t launch_ryser_modp(const uint64_t *atr, const uint64_t *primes, int np
         PERM_RYSER_CASE(16) PERM_RYSER_CASE(17) PERM_RYSER_CASE(18) PERM_RYSER_CASE(19) PERM_RYSER_CASE(20)
         PERM_RYSER_CASE(21) PERM_RYSER_CASE(22) PERM_RYSER_CASE(23) PERM_RYSER_CASE(24) PERM_RYSER_CASE(25)
         PERM_RYSER_CASE(26) PERM_RYSER_CASE(27) PERM_RYSER_CASE(28) PERM_RYSER_CASE(29) PERM_RYSER_CASE(30)
+        PERM_RYSER_CASE(31) PERM_RYSER_CASE(32) PERM_RYSER_CASE(33) PERM_RYSER_CASE(34)
 #undef PERM_RYSER_CASE
     default: return hipErrorInvalidValue;
     }

@@ -20,9 +20,9 @@ LIB_PATH = os.path.join(_HERE, "_lib", "libpermgpu.so")
 
 PERM_INT64 = 0
 PERM_COMPLEX128 = 1
-PERM_N_MAX = 30
+PERM_N_MAX = 34
 PERM_BATCH_N_MAX = 12
-PERM_INT_LIMBS = 32
+PERM_INT_LIMBS = 36
 PERM_MAX_PRIMES = 40
 
 PERM_OK = 0

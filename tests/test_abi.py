@@ -52,14 +52,14 @@ def test_primes_match_oracle(perm):
 
 def test_workspace_bytes(perm):
     from math import comb
-    for n in range(2, 31):
+    for n in range(2, 35):
         b = perm.perm_workspace_bytes(perm.PERM_COMPLEX128, n)
         maxc = max(comb(n, k) for k in range(n + 1))
         assert b >= 2 * 16 * maxc + 16 * n * n
         assert b < 2 * 16 * maxc + 16 * n * n + 4096
         bi = perm.perm_workspace_bytes(perm.PERM_INT64, n)
         assert bi >= 2 * 3 * 8 * maxc
-    assert perm.perm_workspace_bytes(perm.PERM_COMPLEX128, 31) == 0
+    assert perm.perm_workspace_bytes(perm.PERM_COMPLEX128, 35) == 0
     assert perm.perm_workspace_bytes(perm.PERM_COMPLEX128, -1) == 0
     assert perm.perm_workspace_bytes(7, 5) == 0
     # n = 28 complex: two layer tables of C(28,14) entries, about 1.28 GB
@@ -69,15 +69,15 @@ def test_workspace_bytes(perm):
 def test_argument_errors_before_any_device_work(perm):
     L = perm.lib()
     out = perm.perm_c128_t()
-    a = np.zeros((31, 31), dtype=np.complex128)
-    assert L.perm_solve(1, 31, a.ctypes.data, 31, ctypes.byref(out), None, 0, None) == perm.PERM_ERANGE
-    assert "31" in perm.perm_last_error()
-    assert L.perm_solve(1, -1, a.ctypes.data, 31, ctypes.byref(out), None, 0, None) == perm.PERM_EINVAL
+    a = np.zeros((35, 35), dtype=np.complex128)
+    assert L.perm_solve(1, 35, a.ctypes.data, 35, ctypes.byref(out), None, 0, None) == perm.PERM_ERANGE
+    assert "35" in perm.perm_last_error()
+    assert L.perm_solve(1, -1, a.ctypes.data, 35, ctypes.byref(out), None, 0, None) == perm.PERM_EINVAL
     assert L.perm_solve(1, 3, None, 3, ctypes.byref(out), None, 0, None) == perm.PERM_EINVAL
     assert L.perm_solve(1, 3, a.ctypes.data, 2, ctypes.byref(out), None, 0, None) == perm.PERM_EINVAL
     assert L.perm_solve(5, 3, a.ctypes.data, 3, ctypes.byref(out), None, 0, None) == perm.PERM_EINVAL
     assert L.perm_solve(1, 5, a.ctypes.data, 5, ctypes.byref(out), None, 0, None) == perm.PERM_ENOMEM
-    assert L.perm_solve_async(31, None, 31, None, None, 0, None) == perm.PERM_ERANGE
+    assert L.perm_solve_async(35, None, 35, None, None, 0, None) == perm.PERM_ERANGE
     assert L.perm_solve_async(3, None, 3, None, None, 0, None) == perm.PERM_EINVAL
     ns = np.array([3, 13], dtype=np.int32)
     offs = np.array([0, 9], dtype=np.int64)

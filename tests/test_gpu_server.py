@@ -73,7 +73,7 @@ def test_backpressure_and_footprint_errors(P):
             P.perm_server_submit(srv, inputs.complex_gaussian(24, seed=0))
         assert e.value.code == P.PERM_ENOMEM
         with pytest.raises(P.PermError) as e:
-            P.perm_server_submit(srv, np.zeros((31, 31), dtype=np.complex128))
+            P.perm_server_submit(srv, np.zeros((P.PERM_N_MAX + 1, P.PERM_N_MAX + 1), dtype=np.complex128))
         assert e.value.code == P.PERM_ERANGE
         codes, tickets = [], []
         for _ in range(20):
