@@ -267,7 +267,7 @@ static void tune_init_locked() {
 static int default_layer_t(int n) {
     int t = n - 12;
     if (t < 6) t = 6;
-    if (t > 13) t = 13;
+    if (t > 12) t = 12;
     if (t > n) t = n;
     return t;
 }

@@ -25,7 +25,7 @@ namespace permgpu {
 
 constexpr int kNMax = 34;
 constexpr int kTMax = 15;        // largest low window (columns) of a tile
-constexpr int kHighBits = 19;    // largest high part (columns) of a tile (n - t at n = 34, t = 15)
+constexpr int kHighBits = 22;    // largest high part (columns) of a tile (n - t at n = 34, t = 12)
 constexpr int kBatchNMax = 12;   // largest order of the on-chip batched kernel
 constexpr int kRPMax = 3;        // primes that share one integer sweep
 constexpr int kMaxGroups = 32;   // k' groups in one layer launch

@@ -115,12 +115,14 @@ __global__ __launch_bounds__(kRyserBlock) void k_ryser_c128(const double2 *__res
         ryser_product<N>(rr, ri, pr, pi);
         accr = sg * pr;
         acci = sg * pi;
+        // inside the range only columns below m (at most 13) change: 32 bits suffice
+        uint32_t Slo = (uint32_t)S;
         const uint32_t steps = 1u << m;
         for (uint32_t t = 1; t < steps; t++) {
             // next code: column j = ctz(t) enters or leaves S
             const int j = __builtin_ctz(t);
-            S ^= 1ull << j;
-            const double s = ((S >> j) & 1u) ? 1.0 : -1.0;
+            Slo ^= 1u << j;
+            const double s = ((Slo >> j) & 1u) ? 1.0 : -1.0;
             const double2 *col = at + (size_t)j * N;
 #pragma unroll
             for (int i = 0; i < N; i++) {
@@ -247,11 +249,12 @@ __global__ __launch_bounds__(kRyserBlock) void k_ryser_modp(const uint64_t *__re
         bool neg = __builtin_popcountll(S) & 1;
         uint64_t pr = ryser_product_modp<N>(r, p);
         acc = neg ? (pr ? p - pr : 0) : pr;
+        uint32_t Slo = (uint32_t)S;  // only columns below m change
         const uint32_t steps = 1u << m;
         for (uint32_t t = 1; t < steps; t++) {
             const int j = __builtin_ctz(t);
-            S ^= 1ull << j;
-            const bool add = (S >> j) & 1u;
+            Slo ^= 1u << j;
+            const bool add = (Slo >> j) & 1u;
             const uint64_t *col = at + (size_t)j * N;
 #pragma unroll
             for (int i = 0; i < N; i++) {
