@@ -10,7 +10,11 @@ Classical Computers for Five-boson Sampling"):
 * :mod:`oracle.native` -- the same Store-zechin stored sub-permanents in C
   (``perm_oracle.c``): fp64 FMA chain for complex128, exact 128-bit
   accumulation mod p for integers, per(|A|); memo (paper's order) and
-  layers (OpenMP) evaluation.
+  layers (OpenMP) evaluation;
+* repeated columns (bunched bosons): one stored minor per count vector
+  instead of one per subset -- exact (:func:`exact.per_multi_exact`), fp64
+  chain and residues in C (:func:`native.per_multi_c128`,
+  :func:`native.per_multi_int`).
 
 Only ``tests/``, ``__graft_entry__.smoke()`` and the CPU-baseline leg of
 ``bench.py`` may import anything from here.  The oracle shares no code with

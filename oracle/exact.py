@@ -462,3 +462,102 @@ def per_int_multimodular(A, per_mod: Callable[[List[List[int]], int], int],
         if v % p != r:
             raise ArithmeticError("redundant prime disagrees with recombined value")
     return v
+
+
+# --------------------------------------------------------------------------
+# repeated columns (bunched bosons): stored minors over count vectors
+# --------------------------------------------------------------------------
+def _exact_rect(A) -> List[List]:
+    """Exact entries of an n x m matrix (the conversions of as_exact_matrix)."""
+    try:
+        import numpy as np
+    except ImportError:  # pragma: no cover
+        np = None
+    if np is not None and isinstance(A, np.ndarray):
+        if A.ndim != 2:
+            raise ValueError("matrix expected")
+        if np.issubdtype(A.dtype, np.integer) or A.dtype == np.bool_:
+            return [[int(v) for v in row] for row in A]
+        if np.issubdtype(A.dtype, np.complexfloating):
+            return [[GaussQ.from_complex(complex(v)) for v in row] for row in A]
+        if np.issubdtype(A.dtype, np.floating):
+            return [[Fraction(float(v)) for v in row] for row in A]
+        raise TypeError(f"unsupported dtype {A.dtype}")
+    return [[_gq(v) if isinstance(v, complex) else v for v in r] for r in A]
+
+
+def expand_columns(A, mult: Sequence[int]):
+    """The n x n matrix whose columns are column j of the n x m matrix A
+    repeated mult[j] times, in order (a numpy array when A is one)."""
+    mult = [int(t) for t in mult]
+    try:
+        import numpy as np
+        if isinstance(A, np.ndarray):
+            return np.repeat(A, mult, axis=1)
+    except ImportError:  # pragma: no cover
+        pass
+    return [[v for v, t in zip(r, mult) for _ in range(t)] for r in A]
+
+
+def count_vectors(mult: Sequence[int], k: int) -> List[Tuple[int, ...]]:
+    """Every c with 0 <= c_j <= mult[j] and sum(c) = k, ordered by
+    (c_{m-1}, ..., c_0) lexicographically (colex: the last column is the most
+    significant).  This is the order in which a layer of the table is laid out."""
+    out = [c for c in itertools.product(*[range(t + 1) for t in reversed(mult)]) if sum(c) == k]
+    return [tuple(reversed(c)) for c in out]
+
+
+def per_multi_exact(A, mult: Sequence[int]):
+    """per(expand_columns(A, mult)) with one stored minor per count vector.
+
+    Columns j and the copies of it are identical, so every column subset
+    with c_j copies of each column has the same minor (section 4's stored
+    sub-permanents; the repeating terms of Tables 1-3 become one entry):
+        G(c) = sum_{j: c_j > 0} a[|c|-1][j] * G(c - e_j),  G(0) = 1,
+    G counts each assignment of rows to distinct columns once, and each
+    assignment stands for prod_j mult[j]! bijections onto the copies, so
+    per = G(mult) * prod_j mult[j]!.  Exact ints / GaussQ."""
+    M = _exact_rect(A)
+    mult = tuple(int(t) for t in mult)
+    n, m = len(M), len(mult)
+    if any(t < 1 for t in mult) or sum(mult) != n or any(len(r) != m for r in M):
+        raise ValueError("mult must be positive, one per column, summing to the row count")
+    if n == 0:
+        return 1
+    G = {tuple([0] * m): 1}
+    for k in range(1, n + 1):
+        H = {}
+        for c in count_vectors(mult, k):
+            acc = None
+            for j in range(m):
+                if c[j] == 0:
+                    continue
+                prev = c[:j] + (c[j] - 1,) + c[j + 1:]
+                term = M[k - 1][j] * G[prev]
+                acc = term if acc is None else acc + term
+            H[c] = acc
+        G = H
+    scale = 1
+    for t in mult:
+        scale *= math.factorial(t)
+    return G[mult] * scale
+
+
+def per_multi_int_multimodular(A, mult: Sequence[int], g_mod: Callable[[List[List[int]], int], int],
+                               redundant: int = 1) -> int:
+    """Exact integer permanent with repeated columns from residues of G:
+    primes by the bound of the expanded matrix (G divides per, so the bound
+    covers G), G mod p from ``g_mod``, Garner, the redundant primes checked,
+    then times prod_j mult[j]!."""
+    M = _exact_rect(A)
+    B = perm_bound(expand_columns(M, mult))
+    ps = primes_for_bound(B, redundant=redundant)
+    used = ps[: len(ps) - redundant]
+    res = [g_mod([[int(v) % p for v in r] for r in M], p) for p in ps]
+    g = garner(res[: len(used)], used)
+    for r, p in zip(res[len(used):], ps[len(used):]):
+        if g % p != r:
+            raise ArithmeticError("redundant prime disagrees with recombined value")
+    for t in mult:
+        g *= math.factorial(int(t))
+    return g

@@ -63,6 +63,11 @@ def _load() -> ctypes.CDLL:
             lib.oracle_per_modp.restype = ctypes.c_int
             lib.oracle_ryser_bound.argtypes = [ctypes.c_int, dp, ctypes.c_int, ctypes.c_int, ctypes.c_int, dp]
             lib.oracle_ryser_bound.restype = ctypes.c_int
+            ip = ctypes.POINTER(ctypes.c_int32)
+            lib.oracle_multi_c128.argtypes = [ctypes.c_int, ctypes.c_int, ip, dp, ctypes.c_int, dp]
+            lib.oracle_multi_c128.restype = ctypes.c_int
+            lib.oracle_multi_modp.argtypes = [ctypes.c_int, ctypes.c_int, ip, up, ctypes.c_uint64, ctypes.c_int, up]
+            lib.oracle_multi_modp.restype = ctypes.c_int
             lib.oracle_max_threads.argtypes = []
             lib.oracle_max_threads.restype = ctypes.c_int
             _lib = lib
@@ -152,3 +157,53 @@ def per_int(A, mode: int = MODE_LAYERS, nthreads: int = 0, redundant: int = 1) -
 
 def max_threads() -> int:
     return int(_load().oracle_max_threads())
+
+
+# ------------------------------------------------------------ repeated columns
+def _mult_arg(mult, m: int) -> np.ndarray:
+    t = np.ascontiguousarray(np.asarray(mult, dtype=np.int32))
+    if t.ndim != 1 or t.shape[0] != m:
+        raise ValueError("one multiplicity per column")
+    return t
+
+
+def per_multi_c128(A, mult, nthreads: int = 0) -> complex:
+    """fp64 permanent of the matrix with column j of the n x m matrix A
+    repeated mult[j] times: one stored minor per count vector, the complex
+    chain of :func:`per_c128`, then times prod mult[j]! (see perm_oracle.c)."""
+    A = np.ascontiguousarray(np.asarray(A, dtype=np.complex128))
+    if A.ndim != 2:
+        raise ValueError("matrix expected")
+    n, m = A.shape
+    t = _mult_arg(mult, m)
+    out = np.zeros(2, dtype=np.float64)
+    dp = ctypes.POINTER(ctypes.c_double)
+    rc = _load().oracle_multi_c128(n, m, t.ctypes.data_as(ctypes.POINTER(ctypes.c_int32)),
+                                   A.view(np.float64).ctypes.data_as(dp), nthreads, out.ctypes.data_as(dp))
+    _check(rc, "oracle_multi_c128")
+    return complex(out[0], out[1])
+
+
+def multi_modp(R, mult, p: int, nthreads: int = 0) -> int:
+    """G(mult) mod p for an n x m matrix of residues in [0, p) (unscaled)."""
+    R = np.ascontiguousarray(np.asarray(R, dtype=np.uint64))
+    if R.ndim != 2:
+        raise ValueError("matrix expected")
+    n, m = R.shape
+    t = _mult_arg(mult, m)
+    out = np.zeros(1, dtype=np.uint64)
+    up = ctypes.POINTER(ctypes.c_uint64)
+    rc = _load().oracle_multi_modp(n, m, t.ctypes.data_as(ctypes.POINTER(ctypes.c_int32)), R.ctypes.data_as(up),
+                                   ctypes.c_uint64(p), nthreads, out.ctypes.data_as(up))
+    _check(rc, "oracle_multi_modp")
+    return int(out[0])
+
+
+def per_multi_int(A, mult, nthreads: int = 0, redundant: int = 1) -> int:
+    """Exact integer permanent with repeated columns: C residues of G per
+    prime, Garner and the factorial scale in Python."""
+    m = np.asarray(A).shape[1]
+
+    def g_mod(res: List[List[int]], p: int) -> int:
+        return multi_modp(np.array(res, dtype=np.uint64).reshape(len(res), m), mult, p, nthreads=nthreads)
+    return exact.per_multi_int_multimodular(A, mult, g_mod, redundant=redundant)

@@ -383,3 +383,183 @@ int oracle_ryser_bound(int n, const double *a, int mm, int depth, int nthreads, 
     *out = 1.01 * (excess + sqrt(2.0) * gamma_k(depth) * total);
     return 0;
 }
+
+/* ------------------------------------------------------ repeated columns */
+/*
+ * Permanent of the n x n matrix whose columns are column j of the n x m
+ * matrix a repeated mult[j] >= 1 times (sum of mult = n): the output
+ * amplitudes of bunched bosons.  Copies of one column are identical, so
+ * every column subset with the same number c_j of copies of each column has
+ * the same stored minor (section 4's stored sub-permanents, one per count
+ * vector c instead of one per subset):
+ *
+ *     G(c) = sum over j ascending with c_j > 0 of a[|c|-1][j] * G(c - e_j),
+ *     G(e_j) = a[0][j],  G(0) = 1,
+ *
+ * where G(c) counts each assignment of rows 0..|c|-1 to distinct columns
+ * with c_j rows on column j once; an assignment stands for prod_j c_j!
+ * bijections onto the copies, so per = G(mult) * prod_j mult[j]!.
+ * With every mult[j] = 1 the table and the chain are exactly the subset
+ * tables above (same terms in the same order).
+ *
+ * Table: one entry per count vector, mixed-radix index
+ * idx(c) = sum_j c_j * stride_j, stride_0 = 1, stride_{j+1} = stride_j *
+ * (mult[j] + 1).  Evaluation layer by layer (|c| = 2..n), OpenMP within a
+ * layer.  Complex arithmetic: the chain of oracle_per_c128; the result is
+ * G(mult) times f, f = 1.0 multiplied in double by 2, ..., mult[j] for
+ * j = 0, 1, ... in turn (each factor exact while below 2^53), as two real
+ * products.  The mod p variant returns G(mult) mod p (unscaled).
+ */
+#define ORACLE_MULTI_N_MAX 64
+#define ORACLE_MULTI_STATES ((int64_t)1 << 27)
+
+static int multi_layout(int n, int m, const int32_t *mult, int64_t *stride, int64_t *states)
+{
+    if (n < 0 || n > ORACLE_MULTI_N_MAX || m < 0 || m > n || (m > 0 && !mult))
+        return -1;
+    int64_t s = 1, tot = 0;
+    for (int j = 0; j < m; j++) {
+        if (mult[j] < 1)
+            return -1;
+        tot += mult[j];
+        stride[j] = s;
+        s *= (int64_t)mult[j] + 1;
+        if (s > ORACLE_MULTI_STATES)
+            return -2;
+    }
+    stride[m] = s;
+    if (tot != n)
+        return -1;
+    *states = s;
+    return 0;
+}
+
+/* digit sum of every index (the layer it belongs to) */
+static uint8_t *multi_layers(int m, const int32_t *mult, int64_t D)
+{
+    uint8_t *ks = (uint8_t *)malloc((size_t)D);
+    int32_t dig[ORACLE_MULTI_N_MAX] = {0};
+    if (!ks)
+        return NULL;
+    int sum = 0;
+    for (int64_t i = 0; i < D; i++) {
+        ks[i] = (uint8_t)sum;
+        for (int j = 0; j < m; j++) { /* odometer step */
+            if (dig[j] < mult[j]) {
+                dig[j]++;
+                sum++;
+                break;
+            }
+            sum -= dig[j];
+            dig[j] = 0;
+        }
+    }
+    return ks;
+}
+
+int oracle_multi_c128(int n, int m, const int32_t *mult, const double *a, int nthreads, double *out)
+{
+    int64_t stride[ORACLE_MULTI_N_MAX + 1], D;
+    int rc = multi_layout(n, m, mult, stride, &D);
+    if (rc || !out || (n > 0 && !a))
+        return rc ? rc : -1;
+    if (n == 0) {
+        out[0] = 1.0;
+        out[1] = 0.0;
+        return 0;
+    }
+    double *tab = (double *)malloc(2 * (size_t)D * sizeof(double));
+    uint8_t *ks = multi_layers(m, mult, D);
+    if (!tab || !ks) {
+        free(tab);
+        free(ks);
+        return -2;
+    }
+    for (int j = 0; j < m; j++) {
+        tab[2 * stride[j]] = a[2 * j];
+        tab[2 * stride[j] + 1] = a[2 * j + 1];
+    }
+#ifdef _OPENMP
+    if (nthreads > 0)
+        omp_set_num_threads(nthreads);
+#endif
+    for (int k = 2; k <= n; k++) {
+        const double *row = a + 2 * (size_t)(k - 1) * (size_t)m;
+#pragma omp parallel for schedule(static, 4096)
+        for (int64_t idx = 0; idx < D; idx++) {
+            if (ks[idx] != k)
+                continue;
+            double re = 0.0, im = 0.0;
+            for (int j = 0; j < m; j++) {
+                if ((idx / stride[j]) % ((int64_t)mult[j] + 1) == 0)
+                    continue;
+                const int64_t P = idx - stride[j];
+                const double ar = row[2 * j], ai = row[2 * j + 1];
+                const double pr = tab[2 * P], pi = tab[2 * P + 1];
+                re = fma(ar, pr, re);
+                re = fma(-ai, pi, re);
+                im = fma(ar, pi, im);
+                im = fma(ai, pr, im);
+            }
+            tab[2 * idx] = re;
+            tab[2 * idx + 1] = im;
+        }
+    }
+    double f = 1.0;
+    for (int j = 0; j < m; j++)
+        for (int v = 2; v <= mult[j]; v++)
+            f *= (double)v;
+    out[0] = tab[2 * (D - 1)] * f;
+    out[1] = tab[2 * (D - 1) + 1] * f;
+    free(tab);
+    free(ks);
+    return 0;
+}
+
+/* r: n x m residues in [0, p), p < 2^61 (at most 64 products below 2^122
+ * each, so the 128-bit sum cannot overflow); out = G(mult) mod p. */
+int oracle_multi_modp(int n, int m, const int32_t *mult, const uint64_t *r, uint64_t p, int nthreads,
+                      uint64_t *out)
+{
+    int64_t stride[ORACLE_MULTI_N_MAX + 1], D;
+    int rc = multi_layout(n, m, mult, stride, &D);
+    if (rc || !out || (n > 0 && !r) || p < 2 || p >= ((uint64_t)1 << 61))
+        return rc ? rc : -1;
+    for (size_t i = 0; i < (size_t)n * m; i++)
+        if (r[i] >= p)
+            return -1;
+    if (n == 0) {
+        *out = 1 % p;
+        return 0;
+    }
+    uint64_t *tab = (uint64_t *)malloc((size_t)D * sizeof(uint64_t));
+    uint8_t *ks = multi_layers(m, mult, D);
+    if (!tab || !ks) {
+        free(tab);
+        free(ks);
+        return -2;
+    }
+    for (int j = 0; j < m; j++)
+        tab[stride[j]] = r[j];
+#ifdef _OPENMP
+    if (nthreads > 0)
+        omp_set_num_threads(nthreads);
+#endif
+    for (int k = 2; k <= n; k++) {
+        const uint64_t *row = r + (size_t)(k - 1) * (size_t)m;
+#pragma omp parallel for schedule(static, 4096)
+        for (int64_t idx = 0; idx < D; idx++) {
+            if (ks[idx] != k)
+                continue;
+            u128 acc = 0;
+            for (int j = 0; j < m; j++)
+                if ((idx / stride[j]) % ((int64_t)mult[j] + 1) != 0)
+                    acc += (u128)row[j] * tab[idx - stride[j]];
+            tab[idx] = (uint64_t)(acc % p);
+        }
+    }
+    *out = tab[D - 1];
+    free(tab);
+    free(ks);
+    return 0;
+}

@@ -20,7 +20,13 @@ interferometer unitary, section 2):
                              interferometer, whose matrix is not available;
 * :func:`submatrix_batch` -- packed row-major n x n submatrices of a unitary on
                              random distinct rows/columns, n uniform in a range;
-* :func:`poisson_trace`   -- arrival times and sizes of a serving trace.
+* :func:`poisson_trace`   -- arrival times and sizes of a serving trace;
+* :func:`bunched_pattern` -- output counts of n photons landing in `modes`
+                             detectors uniformly at random (collisions
+                             allowed), zero counts dropped;
+* :func:`bunched_output`  -- the n x m matrix of a bunched output: rows = the
+                             n input modes, columns = the m occupied output
+                             modes of a Haar unitary, with their counts.
 """
 from __future__ import annotations
 
@@ -141,3 +147,25 @@ def poisson_trace(U: np.ndarray, count: int, rate_per_s: float, seed: int,
 def split_parts(z: np.ndarray) -> Tuple[np.ndarray, np.ndarray]:
     """Real and imaginary parts as float64 arrays (a convenience for tests)."""
     return np.ascontiguousarray(z.real), np.ascontiguousarray(z.imag)
+
+
+def bunched_pattern(n: int, modes: int, seed: int) -> np.ndarray:
+    """Counts (int32, all >= 1, summing to n) of the occupied modes when n
+    photons land in `modes` detectors independently and uniformly."""
+    hits = _rng(seed).integers(0, modes, size=n)
+    c = np.bincount(hits, minlength=modes)
+    return c[c > 0].astype(np.int32)
+
+
+def bunched_output(n: int, mult, seed: int, modes: int = 0) -> np.ndarray:
+    """n x m complex128 block of a Haar unitary on `modes` >= max(n, m) modes
+    (default 2 * max(n, m)): rows = input modes 0..n-1, columns = m random
+    distinct output modes, one per entry of `mult` (the counts are carried
+    separately).  The output amplitude of the bunched pattern is the permanent
+    of this block with column j repeated mult[j] times, over the square root
+    of prod mult[j]!."""
+    m = len(mult)
+    M = modes or 2 * max(n, m)
+    U = haar_unitary(M, seed)
+    cols = _rng(seed + 1).choice(M, size=m, replace=False)
+    return np.ascontiguousarray(U[:n][:, cols])
