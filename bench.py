@@ -85,7 +85,7 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-extras", action="store_true")
     ap.add_argument("--only", default="",
-                    help="comma list of extra sections to run (n26, ryser, n34, h2h, int30, int10, batch, "
+                    help="comma list of extra sections to run (n26, ryser, n34, h2h, int30, multi, int10, batch, "
                          "serving); "
                          "default: all")
     ap.add_argument("--copy-calibration", action="store_true",
@@ -209,6 +209,8 @@ def extras(perm, inputs, golden, np, torch, log, only=frozenset()):
         _extra_h2h(perm, inputs, out)
     if want("int30"):
         _extra_int30(perm, inputs, golden, log, out)
+    if want("multi"):
+        _extra_multi(perm, inputs, golden, torch, log, out)
     if want("int10"):
         _extra_int10(perm, inputs, np, out)
     if want("batch"):
@@ -346,6 +348,87 @@ def _extra_int30(perm, inputs, golden, log, out):
                                 "verified": (str(v) == g["value"]) if g else None,
                                 "hbm_bytes": layer_bytes(30, 8 * 3)}
     log(f"n=30 0/1 integer: {ms:.2f} ms")
+    del wsi
+
+
+def multi_layer_sizes(mult):
+    """Count vectors per layer: coefficients of prod_j (1 + x + ... + x^mult[j])."""
+    c = [1]
+    for t in mult:
+        d = [0] * (len(c) + int(t))
+        for i, v in enumerate(c):
+            for e in range(int(t) + 1):
+                d[i + e] += v
+        c = d
+    return c
+
+
+def multi_bytes(mult, elem: int = 16) -> int:
+    """Algorithmic HBM bytes of the repeated-column sweep: every stored value
+    of layers 1..n-1 read once, of layers 2..n written once."""
+    w = multi_layer_sizes(mult)
+    return elem * sum(w[k - 1] + w[k] for k in range(2, len(w)))
+
+
+def _extra_multi(perm, inputs, golden, torch, log, out):
+    """Repeated columns: 40 photons landing uniformly in 20 detectors (seed 0),
+    the 40 x m block of a Haar unitary, complex128; and the 36-photon 0/1
+    integer case."""
+    import numpy as np
+    C128 = perm.PERM_COMPLEX128
+    n, M = 40, 20
+    t = inputs.bunched_pattern(n, M, 0)
+    A = inputs.bunched_output(n, t, 0)
+    m = len(t)
+    d_a = torch.from_numpy(A).cuda()
+    d_r = torch.zeros(1, dtype=torch.complex128, device="cuda")
+    ws = perm.device_buffer(perm.perm_multi_workspace_bytes(C128, t))
+    t0 = time.perf_counter()
+    perm.perm_solve_multi_async(n, t, d_a, m, d_r, ws)  # builds and uploads the plan
+    torch.cuda.synchronize()
+    first_ms = (time.perf_counter() - t0) * 1000.0
+    for _ in range(3):
+        perm.perm_solve_multi_async(n, t, d_a, m, d_r, ws)
+    torch.cuda.synchronize()
+    reps = 10
+    t0 = time.perf_counter()
+    for _ in range(reps):
+        perm.perm_solve_multi_async(n, t, d_a, m, d_r, ws)
+    torch.cuda.synchronize()
+    ms = (time.perf_counter() - t0) * 1000.0 / reps
+    perm.perm_profile_enable(True)
+    perm.perm_profile_read()
+    for _ in range(reps):
+        perm.perm_solve_multi_async(n, t, d_a, m, d_r, ws)
+    pr = perm.perm_profile_read()
+    perm.perm_profile_enable(False)
+    z = complex(d_r.cpu().numpy()[0])
+    g = golden.get("multi_c128_n40_M20_s0")
+    verified = (bits(z) == (int(g["re_bits"], 16), int(g["im_bits"], 16))) if g else None
+    kern_ms = pr.multi_c128_ms / reps
+    byts = multi_bytes(t)
+    sizes = multi_layer_sizes(t)
+    out["multi_c128_n40_M20"] = {
+        "ms": round(ms, 4), "first_call_ms": round(first_ms, 2), "kernel_ms": round(kern_ms, 4),
+        "layer_launches": int(pr.multi_c128_launches // reps), "mult": [int(x) for x in t],
+        "count_vectors": int(sum(sizes)), "largest_layer": int(max(sizes)), "algorithmic_bytes": byts,
+        "achieved_gbs": round(byts / (kern_ms * 1e-3) / 1e9, 1),
+        "hbm_frac": round(byts / (kern_ms * 1e-3) / 1e9 / HBM_PEAK_GBS, 4), "verified": verified}
+    log(f"repeated columns n=40 M=20 (m={m}, {sum(sizes):.3g} count vectors): {ms:.3f} ms, kernels {kern_ms:.3f} ms, "
+        f"{byts / (kern_ms * 1e-3) / 1e9:.0f} GB/s algorithmic, first call {first_ms:.1f} ms, verified={verified}")
+    del ws
+    ti = inputs.bunched_pattern(36, 18, 0)
+    B = inputs.bernoulli01(36, seed=0)[:, :len(ti)]
+    wsi = perm.device_buffer(perm.perm_multi_workspace_bytes(perm.PERM_INT64, ti))
+    v = perm.perm_solve_multi(B, ti, workspace=wsi)
+    t0 = time.perf_counter()
+    for _ in range(3):
+        v = perm.perm_solve_multi(B, ti, workspace=wsi)
+    ims = (time.perf_counter() - t0) * 1000.0 / 3
+    gi = golden.get("multi_int_n36_M18_bern_s0")
+    out["multi_int_n36_M18_bernoulli"] = {"ms": round(ims, 3),
+                                          "verified": (str(v) == gi["value"]) if gi else None}
+    log(f"repeated columns 0/1 integer n=36 M=18: {ims:.2f} ms")
     del wsi
 
 

@@ -156,6 +156,82 @@ int perm_ryser(perm_dtype_t dt, int n, const void *a, int64_t lda, void *result,
 int perm_ryser_async(int n, const perm_c128_t *a_dev, int64_t lda, perm_c128_t *result_dev, void *workspace,
                      size_t ws_bytes, void *stream);
 
+/* ------------------------------------------------- repeated columns --- */
+
+#define PERM_MULTI_N_MAX 64  /* largest n accepted by perm_solve_multi */
+
+/* Permanent of the n x n matrix whose columns are column j of the n x m
+ * matrix a repeated mult[j] times, in order (j = 0..m-1): the output
+ * amplitudes of bosons that bunch in the detectors (section 2: an amplitude
+ * is proportional to the permanent of a submatrix of the interferometer
+ * unitary; an output mode hit by t photons contributes its column t times).
+ *
+ * Identical columns give identical stored minors for every column subset
+ * with the same number c_j of copies of each column, so the section-4 table
+ * keeps one value per count vector c (0 <= c_j <= mult[j]) instead of one per
+ * subset:
+ *     G(c) = sum over j ascending with c_j > 0 of a[|c|-1][j] * G(c - e_j),
+ *     G(e_j) = a[0][j],  per = G(mult) * prod_j mult[j]!,
+ * prod_j (mult[j] + 1) values instead of 2^n.  Layer k (|c| = k) is laid out
+ * in colex order of count vectors (the last column most significant); its
+ * size must stay below 2^32.
+ *
+ * Numbers: complex128 uses the perm_solve chain on G, then multiplies both
+ * parts by f = 1.0 * 2 * ... * mult[0] * 2 * ... * mult[1] * ... (in double,
+ * in that order); with every mult[j] = 1 the result is bitwise perm_solve's
+ * (that case runs the subset path).  int64 is exact: G mod the 61-bit primes
+ * (bound of the expanded matrix, one redundant prime), recombined on the
+ * host, times prod_j mult[j]!.
+ *
+ * Arguments: n >= 0 rows (= sum of mult), m distinct columns (0 <= m <= n;
+ * m = 0 only with n = 0), mult host int32_t[m], every entry >= 1; a row-major
+ * a[i*lda + j], lda >= m.
+ * Plan: the tables that map every output to its predecessors depend only on
+ * mult; the library builds them on the host at the first call for a mult,
+ * uploads them once per device into memory it allocates itself, and keeps
+ * them (at most 16 plans and 2 GiB of device copies; the least recently
+ * built is dropped, after a device synchronization).
+ * perm_multi_workspace_bytes: device workspace for (n, m, mult): the matrix
+ * and the pair of largest layers (for int64 per group of primes); 0 when
+ * the arguments are invalid or the layer size or the plan exceeds the limits.
+ * perm_solve_multi: host matrix (perm_c128_t or int64_t) -> host *result
+ * (perm_c128_t or perm_int_t); synchronizes the stream.
+ * perm_solve_multi_async: complex128, device matrix -> device *result_dev,
+ * stream-ordered (the first call for a mult also builds and uploads its plan,
+ * synchronously).
+ * Errors: PERM_EINVAL for a null pointer, lda < m, a multiplicity below 1 or
+ * a sum other than n; PERM_ERANGE for n > PERM_MULTI_N_MAX, every
+ * multiplicity 1 with n > PERM_N_MAX, a layer of 2^32 or more count vectors,
+ * or (int64) a result beyond PERM_INT_LIMBS limbs or PERM_MAX_PRIMES primes;
+ * PERM_ENOMEM for a workspace below perm_multi_workspace_bytes;
+ * PERM_EDEVICE as perm_solve. */
+size_t perm_multi_workspace_bytes(perm_dtype_t dt, int n, int m, const int32_t *mult);
+int perm_solve_multi(perm_dtype_t dt, int n, int m, const int32_t *mult, const void *a, int64_t lda, void *result,
+                     void *workspace, size_t ws_bytes, void *stream);
+int perm_solve_multi_async(int n, int m, const int32_t *mult, const perm_c128_t *a_dev, int64_t lda,
+                           perm_c128_t *result_dev, void *workspace, size_t ws_bytes, void *stream);
+
+/* Shape of the repeated-column plan for (n, m, mult), built on the host (no
+ * device needed).  With check != 0 the plan is also verified against the
+ * closed-form colex ranking of count vectors: every output of every layer
+ * (or, above 2^22 outputs in all, every output of up to 4096-output samples
+ * per layer) is unranked, and the rank of each predecessor c - e_j is
+ * compared with what the tables give; the number of outputs checked is
+ * returned.  PERM_EDEVICE when a check fails (message names the layer and
+ * rank).  With every mult[j] = 1 no plan exists (the subset path runs):
+ * fields are zero except states = 2^n.  */
+typedef struct {
+    int L;                /* low columns (0..L-1) */
+    uint64_t states;      /* prod_j (mult[j] + 1) */
+    uint64_t low_states;  /* prod_{j<L} (mult[j] + 1) */
+    uint32_t max_layer;   /* count vectors in the largest layer */
+    uint64_t tiles;       /* over layers 2..n */
+    uint64_t windows;     /* high windows over layers 2..n */
+    uint64_t plan_bytes;  /* device image of the tables */
+    uint64_t checked;     /* outputs verified */
+} perm_multi_plan_info_t;
+int perm_multi_plan_info(int n, int m, const int32_t *mult, int check, perm_multi_plan_info_t *out);
+
 /* Device workspace bytes for a batch (host array ns of `count` orders). */
 size_t perm_batch_workspace_bytes(perm_dtype_t dt, int count, const int32_t *ns);
 
@@ -270,6 +346,10 @@ typedef struct {
     int64_t batch_launches;
     double ryser_ms;        /* transpose + Gray-code walk + final sum, per call */
     int64_t ryser_launches;
+    double multi_c128_ms;   /* repeated-column layer sweeps, complex, per layer launch */
+    int64_t multi_c128_launches;
+    double multi_modp_ms;   /* the same, residues */
+    int64_t multi_modp_launches;
 } perm_profile_t;
 
 int perm_profile_enable(int on);

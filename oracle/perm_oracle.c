@@ -411,7 +411,7 @@ int oracle_ryser_bound(int n, const double *a, int mm, int depth, int nthreads, 
  * products.  The mod p variant returns G(mult) mod p (unscaled).
  */
 #define ORACLE_MULTI_N_MAX 64
-#define ORACLE_MULTI_STATES ((int64_t)1 << 27)
+#define ORACLE_MULTI_STATES ((int64_t)1 << 29)
 
 static int multi_layout(int n, int m, const int32_t *mult, int64_t *stride, int64_t *states)
 {

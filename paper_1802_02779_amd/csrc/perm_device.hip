@@ -6,3 +6,4 @@
 #include "perm_layer_modp.hip"
 #include "perm_batch.hip"
 #include "perm_ryser.hip"
+#include "perm_multi.hip"

@@ -109,7 +109,7 @@ static bool is_prime64(uint64_t x) {
     return true;
 }
 
-static const std::vector<uint64_t> &primes61() {
+const std::vector<uint64_t> &primes61() {
     static std::vector<uint64_t> ps;
     static std::once_flag once;
     std::call_once(once, [] {
@@ -200,8 +200,10 @@ static Big big_sub(const Big &a, const Big &b) {  // a >= b
 }
 
 // Recombine residues of R primes, lift to (-P/2, P/2], check the redundant
-// prime p[R] against res[R].  Returns PERM_OK or PERM_EDEVICE.
-static int crt_to_int(const uint64_t *res, const uint64_t *p, int R, perm_int_t *out) {
+// prime p[R] against res[R], multiply by the factors in *scale if given.
+// Returns PERM_OK, PERM_EDEVICE (redundant prime) or PERM_ERANGE (limbs).
+int crt_to_int(const uint64_t *res, const uint64_t *p, int R, perm_int_t *out,
+               const std::vector<uint64_t> *scale) {
     std::vector<uint64_t> d;
     garner_digits(res, p, R, d);
     Big v{0}, P{1};
@@ -235,8 +237,13 @@ static int crt_to_int(const uint64_t *res, const uint64_t *p, int R, perm_int_t 
     if (vq != res[R])
         return set_error(PERM_EDEVICE, "redundant prime %llu disagrees with the recombined value",
                          (unsigned long long)q);
+    if (scale && !mag.empty()) {
+        for (uint64_t f : *scale) big_mul_add(mag, f, 0);
+        big_trim(mag);
+    }
     if (mag.size() > PERM_INT_LIMBS)
-        return set_error(PERM_EDEVICE, "result needs %zu limbs (> %d)", mag.size(), PERM_INT_LIMBS);
+        return set_error(scale ? PERM_ERANGE : PERM_EDEVICE, "result needs %zu limbs (> %d)", mag.size(),
+                         PERM_INT_LIMBS);
     std::memset(out, 0, sizeof *out);
     out->sign = sign;
     out->nlimbs = (uint32_t)mag.size();
@@ -1326,9 +1333,15 @@ int perm_profile_read(perm_profile_t *out) {
         } else if (e.kind == 2) {
             out->batch_ms += ms;
             out->batch_launches++;
-        } else {
+        } else if (e.kind == 3) {
             out->ryser_ms += ms;
             out->ryser_launches++;
+        } else if (e.kind == 4) {
+            out->multi_c128_ms += ms;
+            out->multi_c128_launches++;
+        } else {
+            out->multi_modp_ms += ms;
+            out->multi_modp_launches++;
         }
     }
     std::lock_guard<std::mutex> lk(g_prof_mu);

@@ -34,9 +34,19 @@ int solve_c128_device(int n, const void *a_dev, int64_t lda, void *result_dev, v
 // Workspace bytes of the complex path (both solve entry points).
 size_t c128_workspace_bytes(int n);
 
+// The 61-bit primes of the integer paths, largest first.
+const std::vector<uint64_t> &primes61();
+
+// Chinese remaindering of R residues (plus the redundant prime p[R] checked
+// against res[R]) into a signed multi-limb integer, times the factors in
+// *scale when given.
+int crt_to_int(const uint64_t *res, const uint64_t *p, int R, perm_int_t *out,
+               const std::vector<uint64_t> *scale = nullptr);
+
 // Profiling hooks.
 bool profiling_on();
-void profile_record(int kind, hipEvent_t start, hipEvent_t stop);  // kind 0 c128, 1 modp, 2 batch
+// kind 0 c128 layer, 1 modp layer, 2 batch, 3 Ryser, 4 repeated-column c128 layer, 5 its modp layer
+void profile_record(int kind, hipEvent_t start, hipEvent_t stop);
 hipEvent_t profile_event();
 
 // Monotonic clock in seconds.

@@ -23,6 +23,7 @@ PERM_COMPLEX128 = 1
 PERM_N_MAX = 34
 PERM_BATCH_N_MAX = 12
 PERM_INT_LIMBS = 36
+PERM_MULTI_N_MAX = 64
 PERM_MAX_PRIMES = 40
 
 PERM_OK = 0
@@ -49,8 +50,15 @@ EXPORTS = [
     "perm_batch_workspace_bytes", "perm_solve_batch", "perm_server_create",
     "perm_server_submit", "perm_server_poll", "perm_server_destroy", "perm_tuning_get",
     "perm_tuning_set", "perm_tuning_load", "perm_tuning_save", "perm_tuning_key",
-    "perm_profile_enable", "perm_profile_read",
+    "perm_profile_enable", "perm_profile_read", "perm_multi_workspace_bytes", "perm_solve_multi",
+    "perm_solve_multi_async", "perm_multi_plan_info",
 ]
+
+
+class perm_multi_plan_info_t(ctypes.Structure):
+    _fields_ = [("L", ctypes.c_int), ("states", ctypes.c_uint64), ("low_states", ctypes.c_uint64),
+                ("max_layer", ctypes.c_uint32), ("tiles", ctypes.c_uint64), ("windows", ctypes.c_uint64),
+                ("plan_bytes", ctypes.c_uint64), ("checked", ctypes.c_uint64)]
 
 
 class PermError(RuntimeError):
@@ -99,7 +107,9 @@ class perm_profile_t(ctypes.Structure):
     _fields_ = [("layer_c128_ms", ctypes.c_double), ("layer_c128_launches", ctypes.c_int64),
                 ("layer_modp_ms", ctypes.c_double), ("layer_modp_launches", ctypes.c_int64),
                 ("batch_ms", ctypes.c_double), ("batch_launches", ctypes.c_int64),
-                ("ryser_ms", ctypes.c_double), ("ryser_launches", ctypes.c_int64)]
+                ("ryser_ms", ctypes.c_double), ("ryser_launches", ctypes.c_int64),
+                ("multi_c128_ms", ctypes.c_double), ("multi_c128_launches", ctypes.c_int64),
+                ("multi_modp_ms", ctypes.c_double), ("multi_modp_launches", ctypes.c_int64)]
 
 
 _lock = threading.Lock()
@@ -134,6 +144,14 @@ def lib() -> ctypes.CDLL:
         L.perm_ryser.restype = i32
         L.perm_ryser_async.argtypes = [i32, vp, i64, vp, vp, sz, vp]
         L.perm_ryser_async.restype = i32
+        L.perm_multi_workspace_bytes.argtypes = [i32, i32, i32, vp]
+        L.perm_multi_workspace_bytes.restype = sz
+        L.perm_solve_multi.argtypes = [i32, i32, i32, vp, vp, i64, vp, vp, sz, vp]
+        L.perm_solve_multi.restype = i32
+        L.perm_solve_multi_async.argtypes = [i32, i32, vp, vp, i64, vp, vp, sz, vp]
+        L.perm_solve_multi_async.restype = i32
+        L.perm_multi_plan_info.argtypes = [i32, i32, vp, i32, ctypes.POINTER(perm_multi_plan_info_t)]
+        L.perm_multi_plan_info.restype = i32
         L.perm_batch_workspace_bytes.argtypes = [i32, i32, vp]
         L.perm_batch_workspace_bytes.restype = sz
         L.perm_solve_batch.argtypes = [i32, i32, vp, vp, vp, vp, vp, sz, vp, u32]
@@ -288,6 +306,59 @@ def perm_ryser_async(n: int, a_dev, lda: int, result_dev, workspace, stream=None
                                   result_dev.data_ptr(),
                                   workspace.data_ptr() if workspace is not None else None, ws_bytes,
                                   _stream_ptr(stream)))
+
+
+def _mult(mult) -> np.ndarray:
+    t = np.ascontiguousarray(np.asarray(mult, dtype=np.int32))
+    if t.ndim != 1:
+        raise ValueError("one multiplicity per column")
+    return t
+
+
+def perm_multi_workspace_bytes(dtype: int, mult) -> int:
+    """Workspace for a matrix whose column j is repeated mult[j] times (n = sum)."""
+    t = _mult(mult)
+    return int(lib().perm_multi_workspace_bytes(dtype, int(t.sum()), t.shape[0], t.ctypes.data))
+
+
+def perm_solve_multi(A, mult, workspace=None, stream=None):
+    """Permanent of the n x n matrix with column j of the host n x m matrix A
+    repeated mult[j] times (int64 -> Python int, complex128 -> complex)."""
+    A = np.asarray(A)
+    dt = _dtype_of(A)
+    A = np.ascontiguousarray(A, dtype=np.int64 if dt == PERM_INT64 else np.complex128)
+    if A.ndim != 2:
+        raise ValueError("matrix expected")
+    t = _mult(mult)
+    n, m = A.shape
+    need = int(lib().perm_multi_workspace_bytes(dt, n, m, t.ctypes.data))
+    ws = workspace if workspace is not None else (device_buffer(need) if n >= 2 and need else None)
+    ws_ptr = ws.data_ptr() if ws is not None else None
+    ws_bytes = ws.numel() * ws.element_size() if ws is not None else 0
+    s = _stream_ptr(stream) if n >= 2 else None
+    out = perm_int_t() if dt == PERM_INT64 else perm_c128_t()
+    _check(lib().perm_solve_multi(dt, n, m, t.ctypes.data, A.ctypes.data if n else None, max(m, 1),
+                                  ctypes.byref(out), ws_ptr, ws_bytes, s))
+    return out.value() if dt == PERM_INT64 else complex(out.re, out.im)
+
+
+def perm_solve_multi_async(n: int, mult, a_dev, lda: int, result_dev, workspace, stream=None) -> None:
+    """Queue the repeated-column permanent of a device complex128 n x m matrix."""
+    t = _mult(mult)
+    ws_bytes = workspace.numel() * workspace.element_size() if workspace is not None else 0
+    _check(lib().perm_solve_multi_async(n, t.shape[0], t.ctypes.data, a_dev.data_ptr() if a_dev is not None else None,
+                                        lda, result_dev.data_ptr(),
+                                        workspace.data_ptr() if workspace is not None else None, ws_bytes,
+                                        _stream_ptr(stream)))
+
+
+def perm_multi_plan_info(mult, check: bool = False) -> perm_multi_plan_info_t:
+    """Host-only shape (and, with check, verification) of the plan for mult."""
+    t = _mult(mult)
+    out = perm_multi_plan_info_t()
+    _check(lib().perm_multi_plan_info(int(t.sum()), t.shape[0], t.ctypes.data, 1 if check else 0,
+                                      ctypes.byref(out)))
+    return out
 
 
 def perm_batch_workspace_bytes(dtype: int, ns: np.ndarray) -> int:

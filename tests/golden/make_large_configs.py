@@ -9,6 +9,14 @@ Entries (inputs are regenerated from the seeds by the tests):
   c128_n28_s0      28x28 complex Gaussian, seed 0
   int_n30_bern_s0  30x30 Bernoulli(1/2) 0/1 matrix, seed 0 (exact integer)
   int_n10_u09_s*   10x10 uniform {0..9}, seeds 0..15 (exact integer)
+  multi_c128_n{36,40}_M{18,20}_s0
+                   repeated columns: n photons landing uniformly in M
+                   detectors (seed 0), the n x m block of a Haar unitary
+                   (bunched_output, seed 0) with column j repeated mult[j]
+                   times; fp64 chain bit patterns
+  multi_int_n36_M18_bern_s0
+                   the same counts with a 36 x m Bernoulli(1/2) block
+                   (first m columns of bernoulli01(36, seed 0)), exact
 Complex values are stored as the IEEE-754 bit patterns of the oracle's fp64
 FMA chain, plus the oracle's per(|A|) for the relative tolerance.
 """
@@ -39,6 +47,22 @@ def c128_entry(A, threads):
             "per_abs": pa, "oracle_seconds": round(time.time() - t0, 2)}
 
 
+def multi_c128_entry(n, M, seed, threads):
+    t = inputs.bunched_pattern(n, M, seed)
+    A = inputs.bunched_output(n, t, seed)
+    t0 = time.time()
+    z = native.per_multi_c128(A, t, nthreads=threads)
+    bits = np.array([z.real, z.imag], dtype=np.float64).view(np.uint64)
+    return {"re_bits": f"0x{int(bits[0]):016x}", "im_bits": f"0x{int(bits[1]):016x}", "value": [z.real, z.imag],
+            "mult": [int(x) for x in t], "oracle_seconds": round(time.time() - t0, 2)}
+
+
+def multi_int_entry(n, M, seed, threads):
+    t = inputs.bunched_pattern(n, M, seed)
+    B = inputs.bernoulli01(n, seed=seed)[:, :len(t)]
+    return {"value": str(native.per_multi_int(B, t, nthreads=threads)), "mult": [int(x) for x in t]}
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--threads", type=int, default=0)
@@ -58,6 +82,9 @@ def main():
         ("c128_n28_s0", lambda: c128_entry(inputs.complex_gaussian(28, seed=0), args.threads)),
         ("int_n30_bern_s0", lambda: {"value": str(native.per_int(inputs.bernoulli01(30, seed=0),
                                                                   nthreads=args.threads))}),
+        ("multi_c128_n36_M18_s0", lambda: multi_c128_entry(36, 18, 0, args.threads)),
+        ("multi_c128_n40_M20_s0", lambda: multi_c128_entry(40, 20, 0, args.threads)),
+        ("multi_int_n36_M18_bern_s0", lambda: multi_int_entry(36, 18, 0, args.threads)),
     ]
     for key, fn in jobs:
         if args.only and args.only not in key:

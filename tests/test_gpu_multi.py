@@ -1,0 +1,135 @@
+"""GPU parity of the repeated-column path (perm_solve_multi[_async]) against
+the count-vector oracle: complex128 bit for bit (same chain, same scale),
+int64 exact.  Shapes span one tile to many tiles and chunks, ragged layer
+ends, a single column repeated 64 times, and the stored full-size bunched
+workloads (40 photons in 20 detectors: a largest layer of 3.9e7 count
+vectors)."""
+import json
+import math
+import os
+
+import numpy as np
+import pytest
+
+from oracle import exact, native
+from paper_1802_02779_amd import inputs
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def P():
+    import torch
+    assert torch.cuda.is_available(), "GPU tests need a GPU"
+    from paper_1802_02779_amd import perm
+    perm.lib()
+    return perm
+
+
+def bits(z):
+    return np.asarray([z], dtype=np.complex128).view(np.uint64).tolist()
+
+
+SHAPES = [[2], [1, 2], [2, 1, 1], [3, 3], [1] * 12 + [3], [3] + [1] * 12, [2] * 10, [6, 6, 6], [1, 7, 1, 7, 1],
+          [4, 1, 3, 2, 1, 2, 3, 1, 2], [64], [32, 32], [2] * 12 + [1] * 6]
+
+
+@pytest.mark.parametrize("mult", SHAPES, ids=[str(i) for i in range(len(SHAPES))])
+def test_c128_bitwise_equals_oracle(P, mult):
+    n = sum(mult)
+    A = inputs.complex_gaussian(n, seed=n + len(mult))[:, :len(mult)]
+    print(f"[gpu] multi c128 mult={mult}", flush=True)
+    got = P.perm_solve_multi(A, mult)
+    ref = native.per_multi_c128(A, mult)
+    assert bits(got) == bits(ref), (mult, got, ref)
+
+
+@pytest.mark.parametrize("n,M", [(8, 4), (12, 6), (16, 8), (20, 10), (24, 12), (26, 10), (30, 15)])
+def test_c128_bunched_patterns(P, n, M):
+    for seed in range(2):
+        t = inputs.bunched_pattern(n, M, seed)
+        A = inputs.bunched_output(n, t, seed)
+        print(f"[gpu] multi c128 bunched n={n} M={M} seed={seed} mult={t.tolist()}", flush=True)
+        assert bits(P.perm_solve_multi(A, t)) == bits(native.per_multi_c128(A, t)), (n, M, seed)
+
+
+@pytest.mark.parametrize("n", [2, 9, 16, 20])
+def test_all_ones_is_perm_solve(P, n):
+    A = inputs.complex_gaussian(n, seed=50 + n)
+    assert bits(P.perm_solve_multi(A, [1] * n)) == bits(P.perm_solve(A))
+
+
+def test_c128_async_lda_deterministic(P):
+    import torch
+    t = [3, 1, 2, 4, 1, 2, 3]
+    n, m, lda = sum(t), len(t), 11
+    A = inputs.bunched_output(n, t, seed=5)
+    big = np.zeros((n, lda), dtype=np.complex128)
+    big[:, :m] = A
+    d_a = torch.from_numpy(big).cuda()
+    d_r = torch.zeros(2, dtype=torch.complex128, device="cuda")
+    ws = P.device_buffer(P.perm_multi_workspace_bytes(P.PERM_COMPLEX128, t))
+    P.perm_solve_multi_async(n, t, d_a, lda, d_r[0:1], ws)
+    P.perm_solve_multi_async(n, t, d_a, lda, d_r[1:2], ws)
+    r = d_r.cpu().numpy()
+    assert bits(r[0]) == bits(r[1])
+    assert bits(r[0]) == bits(native.per_multi_c128(A, t))
+    small = P.device_buffer(64)
+    with pytest.raises(P.PermError) as e:
+        P.perm_solve_multi(A, t, workspace=small)
+    assert e.value.code == -3  # PERM_ENOMEM
+
+
+def test_c128_small_gaussian_integers_exact(P):
+    rng = np.random.default_rng(77)
+    for t in ([3, 2, 1], [2, 2, 2, 2], [5, 1, 4]):
+        n, m = sum(t), len(t)
+        A = (rng.integers(-1, 2, size=(n, m)) + 1j * rng.integers(-1, 2, size=(n, m))).astype(np.complex128)
+        q = exact.per_multi_exact(A, t)
+        assert P.perm_solve_multi(A, t) == complex(float(q.re), float(q.im)), t
+
+
+@pytest.mark.parametrize("key,n,M", [("multi_c128_n36_M18_s0", 36, 18), ("multi_c128_n40_M20_s0", 40, 20)])
+def test_c128_full_size_stored(P, golden_dir, key, n, M):
+    cfg = json.load(open(os.path.join(golden_dir, "large_configs.json")))[key]
+    t = inputs.bunched_pattern(n, M, 0)
+    assert t.tolist() == cfg["mult"]
+    A = inputs.bunched_output(n, t, 0)
+    print(f"[gpu] multi c128 {key}", flush=True)
+    got = P.perm_solve_multi(A, t)
+    assert bits(got) == [int(cfg["re_bits"], 16), int(cfg["im_bits"], 16)]
+
+
+# ------------------------------------------------------------------ int64
+@pytest.mark.parametrize("mult", [[2, 1], [3, 3], [2] * 8, [4, 1, 3, 2, 1, 2, 3], [1] * 9 + [4], [20], [5, 5, 5, 5]])
+def test_int_exact_vs_oracle(P, mult):
+    rng = np.random.default_rng(sum(mult) * 7 + len(mult))
+    n, m = sum(mult), len(mult)
+    A = rng.integers(-9, 10, size=(n, m), dtype=np.int64)
+    print(f"[gpu] multi int mult={mult}", flush=True)
+    assert P.perm_solve_multi(A, mult) == native.per_multi_int(A, mult), mult
+
+
+def test_int_extreme_entries(P):
+    rng = np.random.default_rng(83)
+    for t in ([2, 1], [1, 3, 1], [6]):
+        n = sum(t)
+        A = rng.integers(-(2 ** 63), 2 ** 63 - 1, size=(n, len(t)), dtype=np.int64, endpoint=True)
+        A[0, 0] = -(2 ** 63)
+        assert P.perm_solve_multi(A, t) == exact.per_multi_exact(A, t), t
+
+
+def test_int_closed_forms(P):
+    t = inputs.bunched_pattern(40, 20, 0)
+    n = 40
+    assert P.perm_solve_multi(np.ones((n, len(t)), dtype=np.int64), t) == math.factorial(n)
+    col = np.arange(1, 41, dtype=np.int64).reshape(40, 1) % 5 + 1
+    assert P.perm_solve_multi(col, [40]) == math.factorial(40) * math.prod(int(v) for v in col[:, 0])
+
+
+def test_int_full_size_stored(P, golden_dir):
+    cfg = json.load(open(os.path.join(golden_dir, "large_configs.json")))["multi_int_n36_M18_bern_s0"]
+    t = inputs.bunched_pattern(36, 18, 0)
+    B = inputs.bernoulli01(36, seed=0)[:, :len(t)]
+    print("[gpu] multi int n=36", flush=True)
+    assert str(P.perm_solve_multi(B, t)) == cfg["value"]

@@ -1,0 +1,128 @@
+"""Host side of the repeated-column path, no GPU: argument checks, sizes,
+and the plan verified against the closed-form colex ranking of count
+vectors (every predecessor rank of every checked output).  CPU only."""
+import ctypes
+import math
+import random
+
+import numpy as np
+import pytest
+
+from oracle import exact
+
+
+@pytest.fixture(scope="module")
+def perm():
+    import os
+    from paper_1802_02779_amd import perm as p
+    if not os.path.exists(p.LIB_PATH):
+        from paper_1802_02779_amd import build
+        build.build()
+    p.lib()
+    return p
+
+
+def layer_sizes(mult):
+    """Coefficients of prod_j (1 + x + ... + x^mult[j])."""
+    c = [1]
+    for t in mult:
+        d = [0] * (len(c) + t)
+        for i, v in enumerate(c):
+            for e in range(t + 1):
+                d[i + e] += v
+        c = d
+    return c
+
+
+def random_mult(rng, n, m):
+    cuts = sorted(rng.sample(range(1, n), m - 1)) if m > 1 else []
+    b = [0] + cuts + [n]
+    return [b[i + 1] - b[i] for i in range(m)]
+
+
+SHAPES = [[2], [3, 1], [1, 2], [5], [2, 2, 2], [1, 1, 1, 2], [4, 1, 3, 2, 1], [1] * 12 + [3],
+          [3] + [1] * 12, [2] * 10, [6, 6, 6], [1, 7, 1, 7, 1], [64], [32, 32], [2] * 14 + [1] * 8]
+
+
+@pytest.mark.parametrize("mult", SHAPES)
+def test_plan_verified_against_colex_ranking(perm, mult):
+    info = perm.perm_multi_plan_info(mult, check=True)
+    sizes = layer_sizes(mult)
+    assert info.states == math.prod(t + 1 for t in mult)
+    assert info.max_layer == max(sizes)
+    assert info.checked > 0
+    assert 1 <= info.L <= len(mult)
+
+
+def test_plan_verified_random_shapes(perm):
+    rng = random.Random(17)
+    for rep in range(40):
+        n = rng.randint(2, 40)
+        m = rng.randint(1, n - 1)
+        mult = random_mult(rng, n, m)
+        if max(layer_sizes(mult)) >= 2 ** 28:
+            continue
+        info = perm.perm_multi_plan_info(mult, check=True)
+        assert info.max_layer == max(layer_sizes(mult)), mult
+
+
+def test_plan_of_the_bunched_workload(perm):
+    from paper_1802_02779_amd import inputs
+    t = inputs.bunched_pattern(36, 18, 0)
+    info = perm.perm_multi_plan_info(t, check=True)
+    assert info.max_layer == max(layer_sizes(t.tolist()))
+    assert info.plan_bytes < 64 << 20
+
+
+def test_count_vector_order_matches_oracle(perm):
+    # the colex order of the oracle's count_vectors is the order the plan checks
+    mult = [2, 1, 2]
+    for k in range(6):
+        assert len(exact.count_vectors(mult, k)) == layer_sizes(mult)[k]
+
+
+def test_all_ones_goes_to_the_subset_path(perm):
+    info = perm.perm_multi_plan_info([1] * 10)
+    assert info.states == 1024 and info.L == 0 and info.tiles == 0
+    assert perm.perm_multi_workspace_bytes(perm.PERM_COMPLEX128, [1] * 20) == \
+        perm.perm_workspace_bytes(perm.PERM_COMPLEX128, 20)
+
+
+def test_workspace_bytes(perm):
+    t = [3, 2, 4, 1, 2, 2, 3]
+    n = sum(t)
+    big = max(layer_sizes(t))
+    b = perm.perm_multi_workspace_bytes(perm.PERM_COMPLEX128, t)
+    assert 2 * 16 * big + 16 * n * len(t) < b < 2 * 16 * big + 16 * n * len(t) + (64 << 20)
+    bi = perm.perm_multi_workspace_bytes(perm.PERM_INT64, t)
+    assert bi >= 2 * 3 * 8 * big
+    assert perm.perm_multi_workspace_bytes(7, t) == 0
+    assert perm.perm_multi_workspace_bytes(perm.PERM_COMPLEX128, [2, 0]) == 0
+
+
+def test_argument_errors(perm):
+    L = perm.lib()
+    out = perm.perm_c128_t()
+    a = np.zeros((70, 70), dtype=np.complex128)
+
+    def call(n, mult, lda=None, dt=1, ptr=a.ctypes.data):
+        t = np.asarray(mult, dtype=np.int32)
+        return L.perm_solve_multi(dt, n, len(t), t.ctypes.data if len(t) else None, ptr,
+                                  lda if lda is not None else max(len(t), 1), ctypes.byref(out), None, 0, None)
+    assert call(5, [2, 2]) == perm.PERM_EINVAL          # sum != n
+    assert call(4, [4, 0]) == perm.PERM_EINVAL          # multiplicity 0
+    assert call(4, [2, 2], lda=1) == perm.PERM_EINVAL   # lda < m
+    assert call(4, [2, 2], ptr=None) == perm.PERM_EINVAL
+    assert call(65, [65]) == perm.PERM_ERANGE
+    assert call(35, [1] * 35) == perm.PERM_ERANGE       # no repeat: the subset path's limit
+    assert call(36, [1] * 34 + [2]) == perm.PERM_ERANGE  # a layer of 2^32 or more
+    assert "2^32" in perm.perm_last_error()
+    assert call(6, [3, 3]) == perm.PERM_ENOMEM          # no workspace, before any device work
+    assert call(6, [3, 3], dt=0) == perm.PERM_ENOMEM
+    assert call(6, [3, 3], dt=5) == perm.PERM_EINVAL
+
+
+def test_trivial_orders_without_device(perm):
+    assert perm.perm_solve_multi(np.zeros((0, 0), dtype=np.complex128), []) == 1
+    assert perm.perm_solve_multi(np.array([[2.5 - 1.0j]]), [1]) == 2.5 - 1.0j
+    assert perm.perm_solve_multi(np.array([[-7]], dtype=np.int64), [1]) == -7
