@@ -27,9 +27,8 @@ namespace permgpu {
 
 namespace {
 
-constexpr uint64_t kLowTarget = 1 << 14;     // low parts wanted per tile group
-constexpr uint64_t kHighMax = 1ull << 20;    // high parts at most
-constexpr uint64_t kPredMax = 1ull << 26;    // lowpred entries at most
+constexpr uint32_t kLowWindow = 2048;        // largest low window wanted (entries)
+constexpr uint64_t kHighMax = 1ull << 22;    // high parts at most
 constexpr uint64_t kPlanMax = 1ull << 30;    // plan bytes at most
 constexpr uint64_t kSat = ~0ull;
 constexpr uint32_t kNone = 0xffffffffu;
@@ -41,17 +40,17 @@ size_t a256(size_t x) { return (x + 255) & ~(size_t)255; }
 typedef unsigned __int128 u128m;
 
 struct MultiPlan {
-    int n = 0, m = 0, L = 0, SL = 0;
+    int n = 0, m = 0, L = 0, SL = 0, SH = 0, tmax1 = 1;
     std::vector<int32_t> mult;
-    uint64_t states = 0, low_states = 0;
+    uint64_t states = 0, low_states = 0, high_states = 0;
     std::vector<uint32_t> size;  // layer sizes, k = 0..n
     uint32_t max_layer = 0;
     std::vector<uint32_t> WL;    // low parts of sum s, s = 0..SL
+    uint32_t max_window = 0;     // max WL
+    std::vector<uint32_t> qoff;  // high parts with |h| = q start at qoff[q] in hlist
     // device image in 32-bit words; every section starts on 256 bytes
     std::vector<uint32_t> blob;
-    size_t low_list = 0, low_off = 0, low_pred = 0;
-    std::vector<size_t> tiles, wins, chunks;  // word offsets of layer k (k >= 2)
-    std::vector<uint32_t> ntiles, nchunks;
+    size_t oG = 0, ohlist = 0, ohstride = 0, ohradix = 0, olp16 = 0, okpoff = 0, oWL = 0;
     uint64_t total_tiles = 0, total_wins = 0;
     // device copies of blob, per device index (guarded by g_plan_mu; freed
     // only when the plan leaves the cache, never at exit)
@@ -76,6 +75,12 @@ size_t section(std::vector<uint32_t> &b) {
     return b.size();
 }
 
+uint32_t max_of(const std::vector<uint64_t> &v, int upto) {
+    uint64_t x = 0;
+    for (int s = 0; s <= upto && s < (int)v.size(); s++) x = std::max(x, v[s]);
+    return (uint32_t)std::min<uint64_t>(x, kNone);
+}
+
 int build_plan(int n, int m, const int32_t *t, MultiPlan &P) {
     P.n = n;
     P.m = m;
@@ -93,33 +98,95 @@ int build_plan(int n, int m, const int32_t *t, MultiPlan &P) {
     for (int j = 0; j < m; j++) PL[j + 1] = sat_mul(PL[j], (uint64_t)t[j] + 1);
     for (int j = m - 1; j >= 0; j--) PH[j] = sat_mul(PH[j + 1], (uint64_t)t[j] + 1);
     P.states = PL[m];
+    // the most low columns whose largest low window stays at kLowWindow
+    // entries; more while the high parts exceed kHighMax (up to the LDS cap)
     int L = 1;
-    while (L < m && PL[L] < kLowTarget) L++;
-    while (L < m && PH[L] > kHighMax) L++;
-    if (PL[L] == kSat || sat_mul(PL[L], (uint64_t)L) > kPredMax || PH[L] > kHighMax)
-        return set_error(PERM_ERANGE, "repeated-column plan too large (%llu low parts, %llu high parts)",
-                         (unsigned long long)PL[L], (unsigned long long)PH[L]);
+    while (L < m && max_of(W[L + 1], n) <= kLowWindow) L++;
+    while (L < m && PH[L] > kHighMax && max_of(W[L + 1], n) <= (uint32_t)kMultiWinMax) L++;
+    if (PH[L] > kHighMax || max_of(W[L], n) > (uint32_t)kMultiWinMax)
+        return set_error(PERM_ERANGE, "repeated-column plan too large (%llu high parts)",
+                         (unsigned long long)PH[L]);
     P.L = L;
     P.low_states = PL[L];
+    P.high_states = PH[L];
     P.SL = 0;
     for (int j = 0; j < L; j++) P.SL += t[j];
+    P.SH = n - P.SL;
     P.WL.assign(P.SL + 1, 0);
-    for (int s = 0; s <= P.SL; s++) P.WL[s] = (uint32_t)W[L][s];  // <= layer size < 2^32
+    for (int s = 0; s <= P.SL; s++) P.WL[s] = (uint32_t)W[L][s];
+    P.max_window = max_of(W[L], n);
+    const int mh = m - L;
+    int tmax = 0;
+    for (int j = L; j < m; j++) tmax = std::max(tmax, (int)t[j]);
+    P.tmax1 = tmax + 1;
+
+    std::vector<uint32_t> &b = P.blob;
+    // G_j(P, c) = sum_{v < c} W_j(P - v) for the high columns
+    P.oG = section(b);
+    for (int j = L; j < m; j++)
+        for (int p = 0; p <= n; p++)
+            for (int c = 0; c <= tmax; c++) {
+                uint64_t g = 0;
+                for (int v = 0; v < c && v <= p; v++) g = sat_add(g, W[j][p - v]);
+                b.push_back((uint32_t)std::min<uint64_t>(g, kNone));
+            }
+    // high parts sorted by |h| (counting sort), then index
+    const uint32_t DH = (uint32_t)PH[L];
+    std::vector<uint8_t> hs(DH);
+    {
+        std::vector<int> d(mh, 0);
+        int q = 0, nz = 0;
+        for (uint32_t x = 0; x < DH; x++) {
+            hs[x] = (uint8_t)q;
+            // tile h is in layers q..q+SL; one high window per nonzero digit
+            const int k0 = std::max(2, q), k1 = std::min(n, q + P.SL);
+            if (k1 >= k0) P.total_wins += (uint64_t)nz * (uint64_t)(k1 - k0 + 1);
+            for (int j = 0; j < mh; j++) {
+                if (d[j] < t[L + j]) {
+                    if (d[j] == 0) nz++;
+                    d[j]++;
+                    q++;
+                    break;
+                }
+                q -= d[j];
+                nz--;
+                d[j] = 0;
+            }
+        }
+    }
+    P.qoff.assign(P.SH + 2, 0);
+    for (uint32_t x = 0; x < DH; x++) P.qoff[hs[x] + 1]++;
+    for (int q = 0; q <= P.SH; q++) P.qoff[q + 1] += P.qoff[q];
+    P.ohlist = section(b);
+    b.resize(b.size() + DH);
+    {
+        std::vector<uint32_t> fill(P.qoff.begin(), P.qoff.end() - 1);
+        for (uint32_t x = 0; x < DH; x++) b[P.ohlist + fill[hs[x]]++] = x;
+    }
+    P.ohstride = section(b);
+    {
+        uint32_t st = 1;
+        for (int j = L; j < m; j++) {
+            b.push_back(st);
+            st *= (uint32_t)t[j] + 1;
+        }
+    }
+    P.ohradix = section(b);
+    for (int j = L; j < m; j++) b.push_back((uint32_t)t[j] + 1);
 
     // low parts: colex order inside each sum is increasing mixed-radix index
     const uint32_t DL = (uint32_t)PL[L];
-    std::vector<uint32_t> cnt(P.SL + 1, 0), rankL(DL), lowoff(P.SL + 2, 0), lowlist(DL),
-        lowpred((size_t)DL * L, kNone);
+    std::vector<uint32_t> cnt(P.SL + 1, 0), rankL(DL);
     std::vector<uint8_t> sumL(DL);
+    std::vector<std::vector<uint32_t>> bysum(P.SL + 1);
     {
         std::vector<int> d(L, 0);
         int sum = 0;
         for (uint32_t v = 0; v < DL; v++) {
             sumL[v] = (uint8_t)sum;
             rankL[v] = cnt[sum]++;
-            for (int i = 0; i < L; i++)
-                if (d[i] > 0) lowpred[(size_t)v * L + i] = rankL[v - (uint32_t)PL[i]];
-            for (int i = 0; i < L; i++) {  // odometer
+            bysum[sum].push_back(v);
+            for (int i = 0; i < L; i++) {
                 if (d[i] < t[i]) {
                     d[i]++;
                     sum++;
@@ -130,126 +197,70 @@ int build_plan(int n, int m, const int32_t *t, MultiPlan &P) {
             }
         }
     }
-    for (int s = 0; s <= P.SL; s++) lowoff[s + 1] = lowoff[s] + cnt[s];
-    for (uint32_t v = 0; v < DL; v++) lowlist[lowoff[sumL[v]] + rankL[v]] = v;
-    std::vector<uint32_t> &b = P.blob;
-    P.low_list = section(b);
-    b.insert(b.end(), lowlist.begin(), lowlist.end());
-    P.low_off = section(b);
-    b.insert(b.end(), lowoff.begin(), lowoff.end());
-    P.low_pred = section(b);
-    b.insert(b.end(), lowpred.begin(), lowpred.end());
-
-    // high parts: tiles of layer k in increasing mixed-radix index of h with
-    // column L least significant (= colex), each of WL[k - |h|] outputs
-    const int mh = m - L;
-    std::vector<uint64_t> SH(mh + 1, 1);
-    for (int j = 0; j < mh; j++) SH[j + 1] = SH[j] * ((uint64_t)t[L + j] + 1);
-    const uint64_t DH = SH[mh];
-    std::vector<int64_t> prevb(DH, -1), curb(DH, -1);
-    P.tiles.assign(n + 1, 0);
-    P.wins.assign(n + 1, 0);
-    P.chunks.assign(n + 1, 0);
-    P.ntiles.assign(n + 1, 0);
-    P.nchunks.assign(n + 1, 0);
-    std::vector<uint32_t> tl, wl, cl;
-    std::vector<int> d(mh, 0);
-    for (int k = 1; k <= n; k++) {
-        tl.clear();
-        wl.clear();
-        std::fill(d.begin(), d.end(), 0);
-        int q = 0;
-        uint64_t base = 0;
-        for (uint64_t x = 0; x < DH; x++) {
-            const int kp = k - q;
-            if (kp < 0 || kp > P.SL) {
-                curb[x] = -1;
-            } else {
-                curb[x] = (int64_t)base;
-                if (k >= 2) {
-                    int64_t lb = 0;
-                    if (kp >= 1) {
-                        lb = prevb[x];
-                        if (lb < 0) return set_error(PERM_EDEVICE, "plan: missing low tile (layer %d)", k);
-                    }
-                    tl.push_back((uint32_t)base);
-                    tl.push_back((uint32_t)kp);
-                    tl.push_back((uint32_t)lb);
-                    tl.push_back((uint32_t)(wl.size() / 2));
-                    for (int j = 0; j < mh; j++) {
-                        if (d[j] == 0) continue;
-                        const int64_t pb = prevb[x - SH[j]];
-                        if (pb < 0) return set_error(PERM_EDEVICE, "plan: missing high tile (layer %d)", k);
-                        wl.push_back((uint32_t)pb);
-                        wl.push_back((uint32_t)(L + j));
-                    }
-                }
-                base += P.WL[kp];
-            }
-            for (int j = 0; j < mh; j++) {  // odometer
-                if (d[j] < t[L + j]) {
-                    d[j]++;
-                    q++;
-                    break;
-                }
-                q -= d[j];
-                d[j] = 0;
+    std::vector<uint16_t> lp;
+    std::vector<uint32_t> kpoff(P.SL + 2, 0);
+    for (int kp = 0; kp <= P.SL; kp++) {
+        kpoff[kp] = (uint32_t)lp.size();
+        const auto &vs = bysum[kp];
+        const size_t base = lp.size();
+        lp.resize(base + (size_t)L * vs.size(), 0xffff);
+        for (size_t r = 0; r < vs.size(); r++) {
+            uint32_t v = vs[r];
+            for (int i = 0; i < L; i++) {
+                const uint32_t digit = (v / (uint32_t)PL[i]) % ((uint32_t)t[i] + 1);
+                if (digit > 0) lp[base + (size_t)i * vs.size() + r] = (uint16_t)rankL[v - (uint32_t)PL[i]];
             }
         }
-        if (base != P.size[k]) return set_error(PERM_EDEVICE, "plan: layer %d size %llu != %u", k,
-                                                (unsigned long long)base, P.size[k]);
-        if (k >= 2) {
-            const uint32_t nt = (uint32_t)(tl.size() / 4);
-            tl.push_back(P.size[k]);
-            tl.push_back(0);
-            tl.push_back(0);
-            tl.push_back((uint32_t)(wl.size() / 2));
-            const uint32_t nch = (P.size[k] + kMultiBlock - 1) / kMultiBlock;
-            cl.assign(nch + 1, 0);
-            uint32_t ti = 0;
-            for (uint32_t c = 0; c < nch; c++) {
-                const uint64_t first = (uint64_t)c * kMultiBlock;
-                while (ti + 1 < nt && tl[4 * (ti + 1)] <= first) ti++;
-                cl[c] = ti;
-            }
-            cl[nch] = nt - 1;  // every tile is nonempty: the last one holds the last output
-            P.tiles[k] = section(b);
-            b.insert(b.end(), tl.begin(), tl.end());
-            P.wins[k] = section(b);
-            b.insert(b.end(), wl.begin(), wl.end());
-            P.chunks[k] = section(b);
-            b.insert(b.end(), cl.begin(), cl.end());
-            P.ntiles[k] = nt;
-            P.nchunks[k] = nch;
-            P.total_tiles += nt;
-            P.total_wins += wl.size() / 2;
-            if ((uint64_t)b.size() * 4 > kPlanMax)
-                return set_error(PERM_ERANGE, "repeated-column plan above %llu bytes", (unsigned long long)kPlanMax);
-        }
-        std::swap(prevb, curb);
     }
+    kpoff[P.SL + 1] = (uint32_t)lp.size();
+    if (lp.size() & 1) lp.push_back(0xffff);
+    P.olp16 = section(b);
+    {
+        const size_t w0 = b.size();
+        b.resize(w0 + lp.size() / 2);
+        std::memcpy(b.data() + w0, lp.data(), lp.size() * 2);
+    }
+    P.okpoff = section(b);
+    b.insert(b.end(), kpoff.begin(), kpoff.end());
+    P.oWL = section(b);
+    b.insert(b.end(), P.WL.begin(), P.WL.end());
     section(b);
+    for (int k = 2; k <= n; k++) {
+        const int qlo = std::max(0, k - P.SL), qhi = std::min(k, P.SH);
+        if (qlo <= qhi) P.total_tiles += P.qoff[qhi + 1] - P.qoff[qlo];
+    }
+    if ((uint64_t)b.size() * 4 > kPlanMax)
+        return set_error(PERM_ERANGE, "repeated-column plan above %llu bytes", (unsigned long long)kPlanMax);
     return PERM_OK;
 }
 
 MultiLayerArgs layer_args(const MultiPlan &P, const char *d_blob, int k) {
     MultiLayerArgs g;
-    g.tiles = (const uint4 *)(d_blob + P.tiles[k] * 4);
-    g.wins = (const uint2 *)(d_blob + P.wins[k] * 4);
-    g.chunk_tile = (const uint32_t *)(d_blob + P.chunks[k] * 4);
-    g.lowlist = (const uint32_t *)(d_blob + P.low_list * 4);
-    g.lowoff = (const uint32_t *)(d_blob + P.low_off * 4);
-    g.lowpred = (const uint32_t *)(d_blob + P.low_pred * 4);
-    g.size = P.size[k];
-    g.nchunks = P.nchunks[k];
-    g.L = P.L;
+    const uint32_t *w = (const uint32_t *)d_blob;
+    g.G = w + P.oG;
+    g.hlist = w + P.ohlist;
+    g.hstride = w + P.ohstride;
+    g.hradix = w + P.ohradix;
+    g.lp16 = (const uint16_t *)(w + P.olp16);
+    g.kpoff = w + P.okpoff;
+    g.WL = w + P.oWL;
+    const int qlo = std::max(0, k - P.SL), qhi = std::min(k, P.SH);
+    g.tile0 = P.qoff[qlo];
+    g.ntiles = qlo <= qhi ? P.qoff[qhi + 1] - P.qoff[qlo] : 0;
+    g.n = P.n;
     g.m = P.m;
+    g.L = P.L;
+    g.SL = P.SL;
+    g.k = k;
+    g.tmax1 = P.tmax1;
     return g;
 }
 
 // ---------------------------------------------------------- plan checker
-// Independent of the builder: closed-form colex rank / unrank of count
-// vectors, compared with what the tables give for each checked output.
+// Closed-form colex rank / unrank of count vectors, written from the
+// definition of the order (independent of the tables), against what a tile
+// of the plan yields: the host mirror of the device's tile decoding below
+// and the 16-bit rank table.
 struct Ranker {
     int n, m;
     const int32_t *t;
@@ -277,89 +288,124 @@ struct Ranker {
     }
 };
 
+struct HostTile {
+    uint32_t base_out, kp, low_base;
+    std::vector<uint32_t> wbase, wcol;
+};
+
+// The device's multi_tile, step for step, on the host.
+HostTile host_tile(const MultiPlan &P, int k, uint32_t x) {
+    const uint32_t *B = P.blob.data();
+    const int mh = P.m - P.L;
+    std::vector<uint32_t> h(mh), a(mh), bb(mh), c(mh);
+    int q = 0;
+    for (int j = 0; j < mh; j++) {
+        h[j] = (x / B[P.ohstride + j]) % B[P.ohradix + j];
+        q += (int)h[j];
+    }
+    const int kp = k - q;
+    int Pj = kp;
+    for (int j = 0; j < mh; j++) {
+        Pj += (int)h[j];
+        const uint32_t *Gj = B + P.oG + (size_t)j * (P.n + 1) * P.tmax1;
+        a[j] = Gj[(size_t)Pj * P.tmax1 + h[j]];
+        bb[j] = Pj >= 1 ? Gj[(size_t)(Pj - 1) * P.tmax1 + h[j]] : 0u;
+        c[j] = h[j] > 0 ? Gj[(size_t)(Pj - 1) * P.tmax1 + h[j] - 1] : 0u;
+    }
+    HostTile T;
+    uint32_t tot_a = 0, tot_b = 0, pa = 0, pb = 0;
+    for (int j = 0; j < mh; j++) {
+        tot_a += a[j];
+        tot_b += bb[j];
+    }
+    for (int j = 0; j < mh; j++) {
+        pa += a[j];
+        pb += bb[j];
+        if (h[j] > 0) {
+            T.wbase.push_back((pa - a[j]) + c[j] + (tot_b - pb));
+            T.wcol.push_back((uint32_t)(P.L + j));
+        }
+    }
+    T.base_out = tot_a;
+    T.kp = (uint32_t)kp;
+    T.low_base = tot_b;
+    return T;
+}
+
 int check_plan(const MultiPlan &P, uint64_t *checked) {
     Ranker rk{P.n, P.m, P.mult.data(), prefix_counts(P.n, P.m, P.mult.data())};
     uint64_t all = 0;
     for (int k = 2; k <= P.n; k++) all += P.size[k];
     const bool full = all <= (1ull << 22);
     const uint32_t *B = P.blob.data();
-    const uint32_t *lowlist = B + P.low_list, *lowoff = B + P.low_off, *lowpred = B + P.low_pred;
-    std::vector<uint64_t> PL(P.L + 1, 1);
-    for (int i = 0; i < P.L; i++) PL[i + 1] = PL[i] * ((uint64_t)P.mult[i] + 1);
+    const uint16_t *lp = (const uint16_t *)(B + P.olp16);
+    const uint32_t *kpoff = B + P.okpoff;
     std::vector<int> c(P.m), e(P.m);
     uint64_t done = 0;
     for (int k = 2; k <= P.n; k++) {
-        const uint32_t size = P.size[k], nt = P.ntiles[k], nch = P.nchunks[k];
-        const uint32_t *T = B + P.tiles[k], *Wn = B + P.wins[k], *C = B + P.chunks[k];
-        // tiles: contiguous, nonempty, sized WL[kp]; sentinel at the end
-        for (uint32_t i = 0; i < nt; i++) {
-            const uint32_t kp = T[4 * i + 1];
-            if ((int)kp > P.SL || T[4 * i] + P.WL[kp] != T[4 * (i + 1)] || T[4 * i + 3] > T[4 * (i + 1) + 3])
-                return set_error(PERM_EDEVICE, "plan check: layer %d tile %u malformed", k, i);
-        }
-        if (T[0] != 0 || T[4 * nt] != size) return set_error(PERM_EDEVICE, "plan check: layer %d tile bounds", k);
-        // chunks: tile of the first output, at most kMultiBlock + 1 tiles each
-        for (uint32_t ch = 0; ch <= nch; ch++) {
-            const uint64_t o = ch < nch ? (uint64_t)ch * kMultiBlock : size - 1;
-            const uint32_t ti = C[ch];
-            if (ti >= nt || T[4 * ti] > o || T[4 * (ti + 1)] <= o)
-                return set_error(PERM_EDEVICE, "plan check: layer %d chunk %u", k, ch);
-            if (ch < nch && C[ch + 1] - C[ch] + 1 > (uint32_t)kMultiBlock + 1)
-                return set_error(PERM_EDEVICE, "plan check: layer %d chunk %u spans too many tiles", k, ch);
-        }
-        const uint32_t step = (full || size <= 4096) ? 1 : std::max<uint32_t>(1, size / 4096);
-        // every `step`-th output and the last one
-        auto after = [&](uint64_t r) -> uint64_t {
-            if (r == size - 1) return size;
-            return r + step < size ? r + step : size - 1;
-        };
-        uint32_t ti = 0;
-        for (uint64_t r = 0; r < size; r = after(r)) {
-            while (T[4 * (ti + 1)] <= r) ti++;
-            rk.unrank(k, r, c);
-            const uint32_t base = T[4 * ti], kp = T[4 * ti + 1], lb = T[4 * ti + 2];
-            const uint32_t w0 = T[4 * ti + 3], w1 = T[4 * (ti + 1) + 3];
-            const uint32_t loc = (uint32_t)(r - base);
-            int sl = 0;
-            for (int i = 0; i < P.L; i++) sl += c[i];
-            if ((uint32_t)sl != kp) return set_error(PERM_EDEVICE, "plan check: layer %d rank %llu low sum", k,
-                                                     (unsigned long long)r);
-            const uint32_t v = lowlist[lowoff[kp] + loc];
-            uint64_t vv = 0;
-            for (int i = 0; i < P.L; i++) vv += (uint64_t)c[i] * PL[i];
-            if (v != vv) return set_error(PERM_EDEVICE, "plan check: layer %d rank %llu low part", k,
-                                          (unsigned long long)r);
-            uint32_t w = w0;
-            for (int j = 0; j < P.m; j++) {
-                if (c[j] == 0) {
-                    if (j < P.L && lowpred[(size_t)v * P.L + j] != kNone)
-                        return set_error(PERM_EDEVICE, "plan check: layer %d rank %llu spurious low %d", k,
-                                         (unsigned long long)r, j);
-                    continue;
+        const MultiLayerArgs g = layer_args(P, (const char *)B, k);
+        // the tiles of a layer cover its ranks exactly once
+        uint64_t covered = 0;
+        const uint32_t tstep = (full || g.ntiles <= 512) ? 1 : g.ntiles / 512;
+        for (uint32_t bi = 0; bi < g.ntiles; bi++) {
+            const HostTile T = host_tile(P, k, B[P.ohlist + g.tile0 + bi]);
+            if ((int)T.kp < 0 || (int)T.kp > P.SL)
+                return set_error(PERM_EDEVICE, "plan check: layer %d tile %u low sum %d", k, bi, (int)T.kp);
+            const uint32_t nout = P.WL[T.kp];
+            covered += nout;
+            if (bi % tstep != 0 && bi + 1 != g.ntiles) continue;
+            if ((uint64_t)T.base_out + nout > P.size[k])
+                return set_error(PERM_EDEVICE, "plan check: layer %d tile %u beyond the layer", k, bi);
+            const uint32_t rstep = (full || nout <= 64) ? 1 : nout / 64;
+            for (uint32_t r = 0; r < nout; r = (r + rstep < nout || r + 1 == nout) ? r + rstep : nout - 1) {
+                const uint64_t rank = (uint64_t)T.base_out + r;
+                rk.unrank(k, rank, c);
+                int sl = 0;
+                for (int i = 0; i < P.L; i++) sl += c[i];
+                if ((uint32_t)sl != T.kp)
+                    return set_error(PERM_EDEVICE, "plan check: layer %d rank %llu is not in tile %u", k,
+                                     (unsigned long long)rank, bi);
+                size_t w = 0;
+                for (int j = 0; j < P.m; j++) {
+                    uint64_t got;
+                    if (j < P.L) {
+                        const uint32_t q16 = lp[kpoff[T.kp] + (size_t)j * nout + r];
+                        if (c[j] == 0) {
+                            if (q16 != 0xffff)
+                                return set_error(PERM_EDEVICE, "plan check: layer %d rank %llu spurious low %d", k,
+                                                 (unsigned long long)rank, j);
+                            continue;
+                        }
+                        if (q16 == 0xffff || T.kp == 0 || q16 >= P.WL[T.kp - 1])
+                            return set_error(PERM_EDEVICE, "plan check: layer %d rank %llu low %d", k,
+                                             (unsigned long long)rank, j);
+                        got = (uint64_t)T.low_base + q16;
+                    } else {
+                        if (c[j] == 0) continue;
+                        if (w >= T.wcol.size() || T.wcol[w] != (uint32_t)j)
+                            return set_error(PERM_EDEVICE, "plan check: layer %d rank %llu window of column %d", k,
+                                             (unsigned long long)rank, j);
+                        got = (uint64_t)T.wbase[w] + r;
+                        w++;
+                    }
+                    e = c;
+                    e[j]--;
+                    const uint64_t want = rk.rank(e);
+                    if (got != want || want >= P.size[k - 1])
+                        return set_error(PERM_EDEVICE, "plan check: layer %d rank %llu column %d: %llu != %llu", k,
+                                         (unsigned long long)rank, j, (unsigned long long)got,
+                                         (unsigned long long)want);
                 }
-                e = c;
-                e[j]--;
-                const uint64_t want = rk.rank(e);
-                uint64_t got;
-                if (j < P.L) {
-                    const uint32_t q = lowpred[(size_t)v * P.L + j];
-                    if (q == kNone) return set_error(PERM_EDEVICE, "plan check: missing low %d", j);
-                    got = (uint64_t)lb + q;
-                } else {
-                    if (w >= w1 || Wn[2 * w + 1] != (uint32_t)j)
-                        return set_error(PERM_EDEVICE, "plan check: layer %d rank %llu window of column %d", k,
-                                         (unsigned long long)r, j);
-                    got = (uint64_t)Wn[2 * w] + loc;
-                    w++;
-                }
-                if (got != want || want >= P.size[k - 1])
-                    return set_error(PERM_EDEVICE, "plan check: layer %d rank %llu column %d: %llu != %llu", k,
-                                     (unsigned long long)r, j, (unsigned long long)got, (unsigned long long)want);
+                if (w != T.wcol.size())
+                    return set_error(PERM_EDEVICE, "plan check: layer %d rank %llu extra windows", k,
+                                     (unsigned long long)rank);
+                done++;
+                if (r + 1 == nout) break;
             }
-            if (w != w1) return set_error(PERM_EDEVICE, "plan check: layer %d rank %llu extra windows", k,
-                                          (unsigned long long)r);
-            done++;
         }
+        if (covered != P.size[k])
+            return set_error(PERM_EDEVICE, "plan check: layer %d tiles cover %llu of %u ranks", k,
+                             (unsigned long long)covered, P.size[k]);
     }
     *checked = done;
     return PERM_OK;
@@ -509,7 +555,7 @@ int multi_c128_device(const MultiPlan &P, const void *a_dev, int64_t lda, void *
             e1 = profile_event();
             if (e0) (void)hipEventRecord(e0, s);
         }
-        MHIP(launch_multi_layer_c128(prev, next, base + Ly.packed + (size_t)(k - 1) * P.m * 16, g, s),
+        MHIP(launch_multi_layer_c128(prev, next, base + Ly.packed + (size_t)(k - 1) * P.m * 16, g, P.max_window, s),
              "repeated-column layer kernel");
         if (prof && e0 && e1) {
             (void)hipEventRecord(e1, s);
@@ -610,7 +656,7 @@ int multi_int(const MultiPlan &P, const int64_t *a, int64_t lda, perm_int_t *out
                 e1 = profile_event();
                 if (e0) (void)hipEventRecord(e0, s);
             }
-            MHIP(launch_multi_layer_modp(prev, next, plane, gred, P.n, k, d_primes + s0, cnt, g, s),
+            MHIP(launch_multi_layer_modp(prev, next, plane, gred, d_primes + s0, cnt, g, s),
                  "repeated-column modp layer kernel");
             if (prof && e0 && e1) {
                 (void)hipEventRecord(e1, s);

@@ -8,47 +8,48 @@
 
 namespace permgpu {
 
-constexpr int kMultiBlock = 256;  // outputs per workgroup (one rank chunk)
-constexpr int kMultiMMax = 64;    // distinct columns
+constexpr int kMultiBlock = 256;     // threads per tile workgroup
+constexpr int kMultiMMax = 64;       // distinct columns
+constexpr int kMultiWinMax = 3072;   // largest low window staged in LDS (entries)
 
-// One layer k of the sweep over count vectors c with |c| = k.  The layer is
-// laid out in colex order (last column most significant).  Columns 0..L-1
-// are "low", L..m-1 "high"; all vectors sharing the high part h form one
-// contiguous tile whose low parts (sum kp = k - |h|) run in colex order.
-//   tiles[i] = {base_out, kp, low_base, win_off} for the layer's tiles in rank
-//              order, then one sentinel {size, 0, 0, total windows}; low_base
-//              is the first rank of tile h in layer k-1 (used when kp > 0);
-//   wins[w]  = {base_in, col}: the tile h - e_col of layer k-1, aligned 1:1
-//              with tile h (same low part, same offset), ascending col;
-//   chunk_tile[c] = the tile holding output c * kMultiBlock, and at
-//              [nchunks] the tile holding the last output;
-//   lowlist  = low parts (mixed-radix index v = sum_i c_i * prod_{i'<i}
-//              (mult[i'] + 1)) grouped by sum, colex within a sum, sum kp
-//              starting at lowoff[kp];
-//   lowpred[v * L + i] = rank of v - e_i among the low parts of its sum, or
-//              0xffffffff when c_i = 0.
+// Layer k of the sweep over count vectors c with |c| = k, in colex order
+// (last column most significant).  Columns 0..L-1 are "low", L..m-1 "high".
+// The vectors sharing a high part h form one contiguous tile; their low
+// parts (sum kp = k - |h|) run in colex order, WL[kp] of them.  The rank of
+// a vector is sum_j G_j(P_j, c_j) with P_j = c_0 + ... + c_j and
+// G_j(P, c) = sum_{v < c} W_j(P - v), W_j(s) = vectors over columns < j
+// with sum s; for a tile's first vector only the high terms are nonzero.
+//   G        [j - L][P][c] for high columns j, P in 0..n, c in 0..tmax;
+//   hlist    high parts as mixed-radix indices (column L least significant),
+//            sorted by |h| then index; those with |h| = q start at qoff[q];
+//   hstride, hradix  per high column: stride of its digit and mult + 1;
+//   lp16     per low sum kp, at kpoff[kp] (16-bit units): L x WL[kp] ranks,
+//            [i][r] = rank of (low part r) - e_i among the low parts of sum
+//            kp - 1, or 0xffff when that low part has no copy of column i;
+//   WL       low parts per sum.
+// Tile b of layer k is hlist[tile0 + b].
 struct MultiLayerArgs {
-    const uint4 *tiles;
-    const uint2 *wins;
-    const uint32_t *chunk_tile;
-    const uint32_t *lowlist;
-    const uint32_t *lowoff;
-    const uint32_t *lowpred;
-    uint32_t size;
-    uint32_t nchunks;
-    int L;
-    int m;
+    const uint32_t *G;
+    const uint32_t *hlist;
+    const uint32_t *hstride;
+    const uint32_t *hradix;
+    const uint16_t *lp16;
+    const uint32_t *kpoff;
+    const uint32_t *WL;
+    uint32_t tile0;
+    uint32_t ntiles;
+    int n, m, L, SL, k, tmax1;
 };
 
 hipError_t launch_multi_pack_c128(const void *a_dev, int64_t lda, int n, int m, void *packed, void *layer1,
                                   hipStream_t s);
 hipError_t launch_multi_layer_c128(const void *prev, void *next, const void *row, const MultiLayerArgs &g,
-                                   hipStream_t s);
+                                   uint32_t max_window, hipStream_t s);
 hipError_t launch_multi_readout_c128(const void *last, double scale, void *out, hipStream_t s);
 // red: residues [prime][n][m]; layer1 planes get row 0.
 hipError_t launch_multi_init_modp(const uint64_t *red, int n, int m, int rp, uint64_t *layer1, size_t plane,
                                   hipStream_t s);
-hipError_t launch_multi_layer_modp(const uint64_t *prev, uint64_t *next, size_t plane, const uint64_t *red, int n,
-                                   int k, const uint64_t *primes, int rp, const MultiLayerArgs &g, hipStream_t s);
+hipError_t launch_multi_layer_modp(const uint64_t *prev, uint64_t *next, size_t plane, const uint64_t *red,
+                                   const uint64_t *primes, int rp, const MultiLayerArgs &g, hipStream_t s);
 
 }  // namespace permgpu

@@ -6,13 +6,16 @@
 // stores one value per count vector c (|c| = k, 0 <= c_j <= mult[j]):
 //     G(c) = sum over j ascending with c_j > 0 of a[k-1][j] * G(c - e_j),
 // the section-4 development along the last row with the repeating terms
-// merged.  One launch per layer; a workgroup computes 256 consecutive ranks.
-// Predecessors of an output in tile h (see perm_multi.h):
-//   * low column i: the tile h of layer k-1, at the rank lowpred gives --
-//     a gather inside one contiguous window;
-//   * high column j: the tile h - e_j of layer k-1 at the same offset -- a
-//     coalesced read of an aligned window.
-// The chain visits the low columns, then the high windows, both ascending,
+// merged.  One launch per layer, one workgroup per tile (high part h):
+//   * the tile's first rank, the first rank of tile h in layer k-1 (its low
+//     predecessors) and of each tile h - e_j (high predecessors) come from
+//     the closed-form colex rank, one lane per high column;
+//   * low predecessors: the window of tile h in layer k-1 is staged in LDS
+//     once; the 16-bit rank table gives each output's offsets, read
+//     coalesced (lanes are consecutive outputs);
+//   * high predecessors: tile h - e_j of layer k-1 at the same offset --
+//     coalesced reads of an aligned window.
+// The chain visits the low columns, then the high columns, both ascending,
 // so the terms come in ascending column order as the definition states.
 #include "perm_multi.h"
 
@@ -36,62 +39,108 @@ hipError_t launch_multi_pack_c128(const void *a_dev, int64_t lda, int n, int m, 
     return hipGetLastError();
 }
 
-// Tile of this workgroup's outputs: the tiles overlapping the chunk go to
-// LDS (at most kMultiBlock + 1 of them, plus the next one for the window
-// end); each lane finds its own by binary search.
-__device__ __forceinline__ uint32_t multi_stage_tiles(const MultiLayerArgs &g, uint4 *s_tile) {
-    const uint32_t c = blockIdx.x;
-    const uint32_t t0 = g.chunk_tile[c];
-    const uint32_t nt = g.chunk_tile[c + 1] - t0 + 1;
-    for (uint32_t i = threadIdx.x; i <= nt; i += kMultiBlock) s_tile[i] = g.tiles[t0 + i];
-    return nt;
+// Per-tile scratch in LDS.
+struct MultiTileLds {
+    uint32_t wbase[kMultiMMax];  // first rank of tile h - e_col in layer k-1, compacted
+    uint32_t wcol[kMultiMMax];   // its column
+    uint32_t base_out, kp, low_base, nh;
+};
+
+__device__ __forceinline__ uint32_t wave_incl_scan(uint32_t v) {
+    const int lane = threadIdx.x & 63;
+#pragma unroll
+    for (int d = 1; d < 64; d <<= 1) {
+        const uint32_t o = __shfl_up(v, d);
+        if (lane >= d) v += o;
+    }
+    return v;
 }
 
-__device__ __forceinline__ uint32_t multi_find_tile(const uint4 *s_tile, uint32_t nt, uint32_t out) {
-    uint32_t lo = 0, hi = nt - 1;
-    while (lo < hi) {
-        const uint32_t mid = (lo + hi + 1) >> 1;
-        if (s_tile[mid].x <= out) lo = mid;
-        else hi = mid - 1;
+// Decodes tile blockIdx.x of layer k and its predecessor tiles into t, in
+// wave 0 with one lane per high column j (prefix sums by shuffles):
+//   P_j  = kp + h_L + ... + h_j,
+//   base = sum_j G_j(P_j, h_j)                       (this tile, layer k),
+//   low  = sum_j G_j(P_j - 1, h_j)                   (tile h, layer k-1, low sum kp-1),
+//   win_j = sum_{i<j} G_i(P_i, h_i) + G_j(P_j - 1, h_j - 1)
+//         + sum_{i>j} G_i(P_i - 1, h_i)               (tile h - e_j, layer k-1).
+// Every thread of the workgroup must call it (it ends with a barrier).
+__device__ __forceinline__ void multi_tile(const MultiLayerArgs &g, MultiTileLds &t) {
+    const int tid = threadIdx.x;
+    if (tid < 64) {
+        const int mh = g.m - g.L;
+        const bool act = tid < mh;
+        const uint32_t x = g.hlist[g.tile0 + blockIdx.x];
+        const uint32_t h = act ? (x / g.hstride[tid]) % g.hradix[tid] : 0u;
+        const uint32_t ph = wave_incl_scan(h);
+        const int kp = g.k - (int)__shfl(ph, 63);
+        const int P = kp + (int)ph;
+        const uint32_t *Gj = g.G + (size_t)(act ? tid : 0) * (g.n + 1) * g.tmax1;
+        const uint32_t a = act ? Gj[(size_t)P * g.tmax1 + h] : 0u;
+        const uint32_t b = (act && P >= 1) ? Gj[(size_t)(P - 1) * g.tmax1 + h] : 0u;
+        const uint32_t c = (act && h > 0) ? Gj[(size_t)(P - 1) * g.tmax1 + h - 1] : 0u;
+        const uint32_t pa = wave_incl_scan(a), pb = wave_incl_scan(b);
+        const uint32_t tot_a = __shfl(pa, 63), tot_b = __shfl(pb, 63);
+        const uint64_t has = __ballot(act && h > 0);
+        if (act && h > 0) {
+            const int slot = __popcll(has & ((1ull << tid) - 1));
+            t.wbase[slot] = (pa - a) + c + (tot_b - pb);
+            t.wcol[slot] = (uint32_t)(g.L + tid);
+        }
+        if (tid == 0) {
+            t.base_out = tot_a;
+            t.kp = (uint32_t)kp;
+            t.low_base = tot_b;
+            t.nh = (uint32_t)__popcll(has);
+        }
     }
-    return lo;
+    __syncthreads();
 }
 
 __global__ __launch_bounds__(kMultiBlock) void k_multi_layer_c128(const double2 *__restrict__ prev,
                                                                  double2 *__restrict__ next,
                                                                  const double2 *__restrict__ row,
                                                                  const MultiLayerArgs g) {
-    __shared__ uint4 s_tile[kMultiBlock + 2];
+    extern __shared__ double2 s_win[];
     __shared__ double2 s_row[kMultiMMax];
-    const uint32_t nt = multi_stage_tiles(g, s_tile);
-    for (int j = threadIdx.x; j < g.m; j += kMultiBlock) s_row[j] = row[j];
+    __shared__ MultiTileLds t;
+    const int tid = threadIdx.x;
+    for (int j = tid; j < g.m; j += kMultiBlock) s_row[j] = row[j];
+    multi_tile(g, t);
+    const uint32_t kp = t.kp, base_out = t.base_out, nh = t.nh;
+    if (kp >= 1) {
+        const uint32_t nwin = g.WL[kp - 1];
+        const double2 *src = prev + t.low_base;
+        for (uint32_t e = tid; e < nwin; e += kMultiBlock) s_win[e] = src[e];
+    }
     __syncthreads();
-    const uint32_t out = blockIdx.x * kMultiBlock + threadIdx.x;
-    if (out >= g.size) return;
-    const uint32_t ti = multi_find_tile(s_tile, nt, out);
-    const uint4 T = s_tile[ti];
-    const uint32_t wend = s_tile[ti + 1].w;
-    const uint32_t r = out - T.x;
-    double re = 0.0, im = 0.0;
-    if (T.y > 0) {
-        const uint32_t v = g.lowlist[g.lowoff[T.y] + r];
-        const uint32_t *pred = g.lowpred + (size_t)v * g.L;
-        for (int i = 0; i < g.L; i++) {
-            const uint32_t q = pred[i];
-            if (q != 0xffffffffu) cfma(re, im, s_row[i], prev[T.z + q]);
+    const uint32_t nout = g.WL[kp];
+    const uint16_t *lp = g.lp16 + g.kpoff[kp];
+    for (uint32_t r = tid; r < nout; r += kMultiBlock) {
+        double re = 0.0, im = 0.0;
+        if (kp >= 1) {
+            for (int i = 0; i < g.L; i++) {
+                const uint32_t q = lp[(size_t)i * nout + r];
+                if (q != 0xffffu) cfma(re, im, s_row[i], s_win[q]);
+            }
         }
+        uint32_t w = 0;
+        for (; w + 4 <= nh; w += 4) {
+            double2 p[4];
+#pragma unroll
+            for (int u = 0; u < 4; u++) p[u] = prev[t.wbase[w + u] + r];
+#pragma unroll
+            for (int u = 0; u < 4; u++) cfma(re, im, s_row[t.wcol[w + u]], p[u]);
+        }
+        for (; w < nh; w++) cfma(re, im, s_row[t.wcol[w]], prev[t.wbase[w] + r]);
+        next[base_out + r] = make_double2(re, im);
     }
-    for (uint32_t w = T.w; w < wend; w++) {
-        const uint2 W = g.wins[w];
-        cfma(re, im, s_row[W.y], prev[W.x + r]);
-    }
-    next[out] = make_double2(re, im);
 }
 
 hipError_t launch_multi_layer_c128(const void *prev, void *next, const void *row, const MultiLayerArgs &g,
-                                   hipStream_t s) {
-    hipLaunchKernelGGL(k_multi_layer_c128, dim3(g.nchunks), dim3(kMultiBlock), 0, s, (const double2 *)prev,
-                       (double2 *)next, (const double2 *)row, g);
+                                   uint32_t max_window, hipStream_t s) {
+    if (max_window > (uint32_t)kMultiWinMax) return hipErrorInvalidValue;
+    hipLaunchKernelGGL(k_multi_layer_c128, dim3(g.ntiles), dim3(kMultiBlock), (size_t)max_window * 16, s,
+                       (const double2 *)prev, (double2 *)next, (const double2 *)row, g);
     return hipGetLastError();
 }
 
@@ -122,63 +171,61 @@ hipError_t launch_multi_init_modp(const uint64_t *red, int n, int m, int rp, uin
 }
 
 // Residues of a[k-1][*] for RP primes; each output sums at most m <= 64
-// products below 2^122 exactly in 128 bits, then one fold.
+// products below 2^122 exactly in 128 bits, then one fold.  Predecessors
+// are read from HBM / cache directly (RP planes rarely fit one LDS window).
 template <int RP>
 __global__ __launch_bounds__(kMultiBlock) void k_multi_layer_modp(const uint64_t *__restrict__ prev,
                                                                  uint64_t *__restrict__ next, size_t plane,
-                                                                 const uint64_t *__restrict__ red, int n, int k,
+                                                                 const uint64_t *__restrict__ red,
                                                                  const uint64_t *__restrict__ primes,
                                                                  const MultiLayerArgs g) {
-    __shared__ uint4 s_tile[kMultiBlock + 2];
     __shared__ uint64_t s_row[RP][kMultiMMax];
-    const uint32_t nt = multi_stage_tiles(g, s_tile);
-    for (int e = threadIdx.x; e < RP * g.m; e += kMultiBlock) {
+    __shared__ MultiTileLds t;
+    const int tid = threadIdx.x;
+    for (int e = tid; e < RP * g.m; e += kMultiBlock) {
         const int r = e / g.m, j = e - r * g.m;
-        s_row[r][j] = red[(size_t)r * n * g.m + (size_t)(k - 1) * g.m + j];
+        s_row[r][j] = red[(size_t)r * g.n * g.m + (size_t)(g.k - 1) * g.m + j];
     }
-    __syncthreads();
-    const uint32_t out = blockIdx.x * kMultiBlock + threadIdx.x;
-    if (out >= g.size) return;
-    const uint32_t ti = multi_find_tile(s_tile, nt, out);
-    const uint4 T = s_tile[ti];
-    const uint32_t wend = s_tile[ti + 1].w;
-    const uint32_t rr = out - T.x;
-    u128 acc[RP];
+    multi_tile(g, t);
+    const uint32_t kp = t.kp, base_out = t.base_out, nh = t.nh, low = t.low_base;
+    const uint32_t nout = g.WL[kp];
+    const uint16_t *lp = g.lp16 + g.kpoff[kp];
+    for (uint32_t rr = tid; rr < nout; rr += kMultiBlock) {
+        u128 acc[RP];
 #pragma unroll
-    for (int r = 0; r < RP; r++) acc[r] = 0;
-    if (T.y > 0) {
-        const uint32_t v = g.lowlist[g.lowoff[T.y] + rr];
-        const uint32_t *pred = g.lowpred + (size_t)v * g.L;
-        for (int i = 0; i < g.L; i++) {
-            const uint32_t q = pred[i];
-            if (q == 0xffffffffu) continue;
+        for (int r = 0; r < RP; r++) acc[r] = 0;
+        if (kp >= 1) {
+            for (int i = 0; i < g.L; i++) {
+                const uint32_t q = lp[(size_t)i * nout + rr];
+                if (q == 0xffffu) continue;
 #pragma unroll
-            for (int r = 0; r < RP; r++) acc[r] += (u128)s_row[r][i] * prev[(size_t)r * plane + T.z + q];
+                for (int r = 0; r < RP; r++) acc[r] += (u128)s_row[r][i] * prev[(size_t)r * plane + low + q];
+            }
         }
-    }
-    for (uint32_t w = T.w; w < wend; w++) {
-        const uint2 W = g.wins[w];
+        for (uint32_t w = 0; w < nh; w++) {
+            const uint32_t col = t.wcol[w], b = t.wbase[w];
 #pragma unroll
-        for (int r = 0; r < RP; r++) acc[r] += (u128)s_row[r][W.y] * prev[(size_t)r * plane + W.x + rr];
-    }
+            for (int r = 0; r < RP; r++) acc[r] += (u128)s_row[r][col] * prev[(size_t)r * plane + b + rr];
+        }
 #pragma unroll
-    for (int r = 0; r < RP; r++) next[(size_t)r * plane + out] = fold61(acc[r], primes[r]);
+        for (int r = 0; r < RP; r++) next[(size_t)r * plane + base_out + rr] = fold61(acc[r], primes[r]);
+    }
 }
 
-hipError_t launch_multi_layer_modp(const uint64_t *prev, uint64_t *next, size_t plane, const uint64_t *red, int n,
-                                   int k, const uint64_t *primes, int rp, const MultiLayerArgs &g, hipStream_t s) {
+hipError_t launch_multi_layer_modp(const uint64_t *prev, uint64_t *next, size_t plane, const uint64_t *red,
+                                   const uint64_t *primes, int rp, const MultiLayerArgs &g, hipStream_t s) {
     switch (rp) {
     case 1:
-        hipLaunchKernelGGL(k_multi_layer_modp<1>, dim3(g.nchunks), dim3(kMultiBlock), 0, s, prev, next, plane, red,
-                           n, k, primes, g);
+        hipLaunchKernelGGL(k_multi_layer_modp<1>, dim3(g.ntiles), dim3(kMultiBlock), 0, s, prev, next, plane, red,
+                           primes, g);
         break;
     case 2:
-        hipLaunchKernelGGL(k_multi_layer_modp<2>, dim3(g.nchunks), dim3(kMultiBlock), 0, s, prev, next, plane, red,
-                           n, k, primes, g);
+        hipLaunchKernelGGL(k_multi_layer_modp<2>, dim3(g.ntiles), dim3(kMultiBlock), 0, s, prev, next, plane, red,
+                           primes, g);
         break;
     case 3:
-        hipLaunchKernelGGL(k_multi_layer_modp<3>, dim3(g.nchunks), dim3(kMultiBlock), 0, s, prev, next, plane, red,
-                           n, k, primes, g);
+        hipLaunchKernelGGL(k_multi_layer_modp<3>, dim3(g.ntiles), dim3(kMultiBlock), 0, s, prev, next, plane, red,
+                           primes, g);
         break;
     default:
         return hipErrorInvalidValue;
