@@ -408,12 +408,21 @@ def _extra_multi(perm, inputs, golden, torch, log, out):
     kern_ms = pr.multi_c128_ms / reps
     byts = multi_bytes(t)
     sizes = multi_layer_sizes(t)
+    traffic = None
+    cfile = os.path.join(ROOT, "profiles", "multi_c128_n40_counters.json")
+    if os.path.exists(cfile):
+        from paper_1802_02779_amd.profiling import multi_source_hash
+        with open(cfile) as f:
+            cnt = json.load(f)
+        if cnt.get("source_hash") == multi_source_hash(ROOT) and cnt.get("mult") == [int(x) for x in t]:
+            traffic = cnt.get("hbm_bytes_per_solve")
     out["multi_c128_n40_M20"] = {
         "ms": round(ms, 4), "first_call_ms": round(first_ms, 2), "kernel_ms": round(kern_ms, 4),
         "layer_launches": int(pr.multi_c128_launches // reps), "mult": [int(x) for x in t],
         "count_vectors": int(sum(sizes)), "largest_layer": int(max(sizes)), "algorithmic_bytes": byts,
         "achieved_gbs": round(byts / (kern_ms * 1e-3) / 1e9, 1),
-        "hbm_frac": round(byts / (kern_ms * 1e-3) / 1e9 / HBM_PEAK_GBS, 4), "verified": verified}
+        "hbm_frac": round(byts / (kern_ms * 1e-3) / 1e9 / HBM_PEAK_GBS, 4), "traffic_bytes": traffic,
+        "verified": verified}
     log(f"repeated columns n=40 M=20 (m={m}, {sum(sizes):.3g} count vectors): {ms:.3f} ms, kernels {kern_ms:.3f} ms, "
         f"{byts / (kern_ms * 1e-3) / 1e9:.0f} GB/s algorithmic, first call {first_ms:.1f} ms, verified={verified}")
     del ws

@@ -27,7 +27,7 @@ namespace permgpu {
 
 namespace {
 
-constexpr uint32_t kLowWindow = 2048;        // largest low window wanted (entries)
+constexpr uint32_t kLowWindow = 1024;        // largest low window wanted (entries)
 constexpr uint64_t kHighMax = 1ull << 22;    // high parts at most
 constexpr uint64_t kPlanMax = 1ull << 30;    // plan bytes at most
 constexpr uint64_t kSat = ~0ull;

@@ -56,6 +56,20 @@ __device__ __forceinline__ uint32_t wave_incl_scan(uint32_t v) {
     return v;
 }
 
+// Workgroup -> tile: runs of kMultiXcdRun consecutive tiles on one XCD
+// (workgroups are dealt to the 8 XCDs in turn), so tiles that read the same
+// predecessor windows share that XCD's L2; 0 keeps the identity.
+constexpr uint32_t kMultiXcdRun = 64;
+
+__device__ __forceinline__ uint32_t multi_tile_index(uint32_t ntiles) {
+    const uint32_t b = blockIdx.x;
+    if (kMultiXcdRun == 0) return b;
+    const uint32_t span = 8u * kMultiXcdRun;
+    if (b >= (ntiles / span) * span) return b;
+    const uint32_t r = b % span;
+    return (b - r) + (r % 8u) * kMultiXcdRun + r / 8u;
+}
+
 // Decodes tile blockIdx.x of layer k and its predecessor tiles into t, in
 // wave 0 with one lane per high column j (prefix sums by shuffles):
 //   P_j  = kp + h_L + ... + h_j,
@@ -69,7 +83,7 @@ __device__ __forceinline__ void multi_tile(const MultiLayerArgs &g, MultiTileLds
     if (tid < 64) {
         const int mh = g.m - g.L;
         const bool act = tid < mh;
-        const uint32_t x = g.hlist[g.tile0 + blockIdx.x];
+        const uint32_t x = g.hlist[g.tile0 + multi_tile_index(g.ntiles)];
         const uint32_t h = act ? (x / g.hstride[tid]) % g.hradix[tid] : 0u;
         const uint32_t ph = wave_incl_scan(h);
         const int kp = g.k - (int)__shfl(ph, 63);

@@ -44,7 +44,7 @@ def main():
         print(f"\nsum of the step's layer launches: {tot / 1e6:.3f} ms")
 
 
-if __name__ == "__main__" and not (len(sys.argv) > 1 and sys.argv[1] == "counters"):
+if __name__ == "__main__" and not (len(sys.argv) > 1 and sys.argv[1] in ("counters", "multi-counters")):
     main()
 
 
@@ -120,6 +120,92 @@ def counters(fetch_db: str, write_db: str, cmd: str, root: str, n: int = 28, ext
             "write_bytes_per_step": int(tw), "algorithmic_bytes_per_step": int(ta),
             "fetch_factor": ff, "write_factor": wf}
     return "\n".join(lines) + "\n", data
+
+
+def multi_source_hash(root: str) -> str:
+    """Hash of what decides the repeated-column sweep's memory traffic: its
+    kernel and plan sources."""
+    import hashlib
+    import os
+    h = hashlib.sha256()
+    csrc = os.path.join(root, "paper_1802_02779_amd", "csrc")
+    for f in ("perm_multi.hip", "perm_multi.cpp", "perm_multi.h", "perm_layer_c128.hip"):
+        with open(os.path.join(csrc, f), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()[:16]
+
+
+def multi_layer_sizes(mult):
+    """Count vectors per layer: coefficients of prod_j (1 + x + ... + x^mult[j])."""
+    c = [1]
+    for t in mult:
+        d = [0] * (len(c) + int(t))
+        for i, v in enumerate(c):
+            for e in range(int(t) + 1):
+                d[i + e] += v
+        c = d
+    return c
+
+
+def multi_counters(fetch_db: str, write_db: str, hit_db: str, cmd: str, root: str, mult):
+    """HBM traffic of one repeated-column complex solve (the last one in the
+    run) from three rocprofv3 --pmc runs, scaled by the 1 GiB copy the run
+    starts with, per layer and in total.  Returns (markdown, json-able dict)."""
+    import collections
+
+    W = multi_layer_sizes(mult)
+    n = len(W) - 1
+
+    def load(db):
+        cur = sqlite3.connect(db).cursor()
+        rows = list(cur.execute("select dispatch_id, kernel_name, grid_size, counter_name, value "
+                                "from counters_collection order by dispatch_id"))
+        cal, lay = {}, collections.OrderedDict()
+        for d, k, g, c, v in rows:
+            if "copyBuffer" in k and g == 131072:
+                cal[c] = v
+            if "k_multi_layer_c128" in k:
+                lay.setdefault(d, {})[c] = v
+        return cal, list(lay.values())[-(n - 1):]
+
+    fcal, fl = load(fetch_db)
+    wcal, wl = load(write_db)
+    _, hl = load(hit_db)
+    ff = 1048576.0 / fcal["FETCH_SIZE"]
+    wf = 1048576.0 / wcal["WRITE_SIZE"]
+    lines = [f"commands:\n\n    {cmd}\n",
+             f"workload: column multiplicities {list(map(int, mult))} (n = {n}, {sum(W)} count vectors)\n",
+             f"calibration (1 GiB device copy): FETCH_SIZE factor {ff:.4f}, WRITE_SIZE factor {wf:.4f}\n",
+             "| layer k | algorithmic read MB | fetched MB | algorithmic write MB | written MB | L2 hit |",
+             "|---|---|---|---|---|---|"]
+    tf = tw = ta = hits = misses = 0.0
+    for i, k in enumerate(range(2, n + 1)):
+        ar, aw = 16 * W[k - 1], 16 * W[k]
+        f = fl[i]["FETCH_SIZE"] * 1024 * ff
+        w = wl[i]["WRITE_SIZE"] * 1024 * wf
+        h, m = hl[i]["TCC_HIT_sum"], hl[i]["TCC_MISS_sum"]
+        tf, tw, ta, hits, misses = tf + f, tw + w, ta + ar + aw, hits + h, misses + m
+        lines.append(f"| {k} | {ar / 1e6:.1f} | {f / 1e6:.1f} | {aw / 1e6:.1f} | {w / 1e6:.1f} | "
+                     f"{h / max(h + m, 1):.3f} |")
+    lines.append(f"\nper solve: fetched {tf / 1e9:.2f} GB, written {tw / 1e9:.2f} GB, algorithmic "
+                 f"{ta / 1e9:.2f} GB, amplification {(tf + tw) / ta:.2f}, L2 hit rate {hits / (hits + misses):.3f}")
+    data = {"source_hash": multi_source_hash(root), "mult": [int(x) for x in mult], "launches": n - 1,
+            "hbm_bytes_per_solve": int(tf + tw), "fetch_bytes_per_solve": int(tf), "write_bytes_per_solve": int(tw),
+            "algorithmic_bytes_per_solve": int(ta), "fetch_factor": ff, "write_factor": wf}
+    return "\n".join(lines) + "\n", data
+
+
+if __name__ == "__main__" and len(sys.argv) > 1 and sys.argv[1] == "multi-counters":
+    import json
+    import os
+    root = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+    sys.path.insert(0, root)
+    from paper_1802_02779_amd import inputs
+    md, data = multi_counters(sys.argv[2], sys.argv[3], sys.argv[4], sys.argv[5], root,
+                              inputs.bunched_pattern(40, 20, 0))
+    print(md)
+    with open(os.path.join(root, "profiles", "multi_c128_n40_counters.json"), "w") as f:
+        json.dump(data, f, indent=1)
 
 
 if __name__ == "__main__" and len(sys.argv) > 1 and sys.argv[1] == "counters":
