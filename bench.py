@@ -12,7 +12,8 @@ layer sweep) measured with HIP events on its own stream, and the oracle timed
 on the host's cores.  Extra fields cover the other workloads: the 26x26
 complex and 30x30 0/1 integer solves, the 10x10 integer solve, the batched
 2^20 submatrix workload against a plain per-matrix loop, and the serving
-trace.  Progress goes to stderr.
+trace, Ryser's eq. (4) at n = 28 and 34, n = 34 Store-zechin, and the
+repeated-column (bunched-boson) solves.  Progress goes to stderr.
 """
 from __future__ import annotations
 
