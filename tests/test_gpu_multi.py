@@ -133,3 +133,41 @@ def test_int_full_size_stored(P, golden_dir):
     B = inputs.bernoulli01(36, seed=0)[:, :len(t)]
     print("[gpu] multi int n=36", flush=True)
     assert str(P.perm_solve_multi(B, t)) == cfg["value"]
+
+
+# ------------------------------------------------------- maximum sizes
+U64 = 2.0 ** -53
+BIG = [2] * 20 + [1] * 2  # n = 42, largest layer 1.48e9 count vectors (47 GB of layer pair)
+
+
+def chain_error_bound(n):
+    e = 0.0
+    for k in range(2, n + 1):
+        g = 2 * k * U64 / (1 - 2 * k * U64)
+        e = e + math.sqrt(2.0) * g * (1 + e)
+    return e
+
+
+def test_c128_rank_one_largest_layers(P):
+    """Rank one u v^T: per = n! prod u_i prod v_j^mult[j]; per(|A|) = |per|,
+    so the chain bound applies relative to |per| (plus the rounding of the
+    scale and of the reference itself)."""
+    import torch
+    n, m = sum(BIG), len(BIG)
+    rng = np.random.default_rng(42)
+    u = np.exp(1j * rng.uniform(0, 2 * np.pi, n)) * rng.uniform(0.8, 1.2, n)
+    v = np.exp(1j * rng.uniform(0, 2 * np.pi, m)) * rng.uniform(0.8, 1.2, m)
+    A = np.outer(u, v)
+    print(f"[gpu] multi c128 rank one n={n} m={m}", flush=True)
+    z = P.perm_solve_multi(A, BIG)
+    torch.cuda.empty_cache()
+    ref = math.factorial(n) * np.prod(u) * np.prod(v ** np.array(BIG))
+    assert abs(z - ref) <= (chain_error_bound(n) + (4 * n + 8) * U64) * abs(ref)
+
+
+def test_int_all_ones_largest_layers(P):
+    import torch
+    n, m = sum(BIG), len(BIG)
+    print(f"[gpu] multi int all-ones n={n} m={m}", flush=True)
+    assert P.perm_solve_multi(np.ones((n, m), dtype=np.int64), BIG) == math.factorial(n)
+    torch.cuda.empty_cache()
