@@ -28,6 +28,7 @@ import numpy as np
 
 HERE = os.path.dirname(os.path.abspath(__file__))
 DEFAULT_FILE = os.path.join(HERE, "tuning", "gfx950.json")
+HIGH_BITS = 22  # the library's largest tile high part: n - t above it is rejected
 
 
 def _time_ms(fn, reps: int, sync) -> float:
@@ -42,7 +43,11 @@ def _time_ms(fn, reps: int, sync) -> float:
     return float(np.median(ts))
 
 
-def tune_layer(perm, inputs, torch, n: int, log=print, reps: int = 3):
+def _log(msg):
+    print(msg, flush=True)
+
+
+def tune_layer(perm, inputs, torch, n: int, log=_log, reps: int = 3):
     C = perm.PERM_COMPLEX128
     A = inputs.complex_gaussian(n, seed=n)
     d_a = torch.from_numpy(A).cuda()
@@ -59,11 +64,14 @@ def tune_layer(perm, inputs, torch, n: int, log=print, reps: int = 3):
     ref_ms = _time_ms(run, reps, torch.cuda.synchronize)
     ref = d_r.cpu().numpy().view(np.uint64).copy()
     best = (ref_ms, 0, -1, 0, 0)
-    t_lo, t_hi = max(1, n - 17, n - 19), min(15, n)
+    # above n = 30 one solve takes 40-400 ms: a smaller grid
+    big = n > 30
+    t_lo, t_hi = max(1, n - HIGH_BITS), min(14 if big else 15, n)
     for t in range(max(t_lo, 8), t_hi + 1):
-        for chunk in (0, 16, 64, 256):
+        log(f"  n={n} t={t} ...")
+        for chunk in ((64, 256) if big else (0, 16, 64, 256)):
             for nt in (0, 1):
-                for thin in (-1, 128, 512):
+                for thin in ((-1, 128) if big else (-1, 128, 512)):
                     cand = perm.perm_tuning_t.from_buffer_copy(default)
                     cand.layer_t[n] = t
                     cand.layer_xcd_remap[n] = chunk
@@ -86,7 +94,7 @@ def tune_layer(perm, inputs, torch, n: int, log=print, reps: int = 3):
     return best
 
 
-def tune_batch(perm, inputs, torch, n: int, count: int = 1 << 15, log=print, reps: int = 5):
+def tune_batch(perm, inputs, torch, n: int, count: int = 1 << 15, log=_log, reps: int = 5):
     C = perm.PERM_COMPLEX128
     U = inputs.haar_unitary(64, seed=2018)
     b = inputs.submatrix_batch(U, count, n, n, seed=n)
@@ -135,6 +143,7 @@ def main(argv=None):
         perm.perm_tuning_load(args.out)
     for n in [int(x) for x in args.layer_n.split(",") if x]:
         tune_layer(perm, inputs, torch, n)
+        torch.cuda.empty_cache()
     if args.batch:
         for n in range(3, 13):
             tune_batch(perm, inputs, torch, n)
