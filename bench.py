@@ -174,7 +174,26 @@ def main():
                 "algorithmic_bytes_per_launch": int(bytes_per_launch),
                 "fp64_tflops": round(flops_per_step / (kern_ms_per_step * 1e-3) / 1e12, 3),
                 "fp64_frac": round(flops_per_step / (kern_ms_per_step * 1e-3) / 1e12 / FP64_PEAK_TFLOPS, 4)}
-    log(f"layer sweep: avg {avg_ms:.4f} ms/launch, {achieved:.0f} GB/s algorithmic")
+    # what the memory system delivers to a plain stream: a 1 GiB device-to-
+    # device copy (read + write bytes over its time), next to the rate at
+    # which the sweep moves its measured traffic
+    src = torch.empty(1 << 30, dtype=torch.uint8, device="cuda")
+    dst = torch.empty_like(src)
+    dst.copy_(src)
+    torch.cuda.synchronize()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record()
+    for _ in range(5):
+        dst.copy_(src)
+    e1.record()
+    torch.cuda.synchronize()
+    copy_gbs = 2 * (1 << 30) * 5 / (e0.elapsed_time(e1) * 1e-3) / 1e9
+    del src, dst
+    roofline["copy_gbs"] = round(copy_gbs, 1)
+    if traffic:
+        roofline["traffic_gbs"] = round(traffic / (avg_ms * 1e-3) / 1e9, 1)
+    log(f"layer sweep: avg {avg_ms:.4f} ms/launch, {achieved:.0f} GB/s algorithmic; "
+        f"measured traffic at {roofline.get('traffic_gbs')} GB/s, plain 1 GiB copy {copy_gbs:.0f} GB/s")
 
     result = {
         "metric": METRIC, "value": round(1000.0 / ms_per_step, 3), "unit": "perms/s", "n_gpus": 1,
