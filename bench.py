@@ -298,12 +298,15 @@ def _extra_ryser(perm, inputs, torch, log, out):
     r = d_r.cpu().numpy()
     rms = pr.ryser_ms / max(1, pr.ryser_launches)
     rflops = ryser_flops(n)
+    probe = perm.perm_probe_fp64()
     out["ryser_c128_n28"] = {"ms": round(rms, 4), "fp64_tflops": round(rflops / rms / 1e9, 3),
                              "fp64_frac": round(rflops / rms / 1e9 / FP64_PEAK_TFLOPS, 4),
                              "issue_bound_frac": round(ryser_issue_bound(n), 4),
+                             "fp64_probe_tflops": round(probe, 2),
+                             "fp64_frac_of_probe": round(rflops / rms / 1e9 / probe, 4),
                              "rel_diff_vs_store_zechin": float(abs(r[0] - r[1]) / abs(r[1]))}
-    log(f"Ryser n=28: {rms:.3f} ms ({rflops / rms / 1e9:.1f} TFLOP/s), rel. diff. to Store-zechin "
-        f"{abs(r[0] - r[1]) / abs(r[1]):.2e}")
+    log(f"Ryser n=28: {rms:.3f} ms ({rflops / rms / 1e9:.1f} TFLOP/s; FMA probe {probe:.1f} TFLOP/s), "
+        f"rel. diff. to Store-zechin {abs(r[0] - r[1]) / abs(r[1]):.2e}")
 
 
 def _extra_n34(perm, inputs, torch, log, out):

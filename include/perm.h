@@ -232,6 +232,14 @@ typedef struct {
 } perm_multi_plan_info_t;
 int perm_multi_plan_info(int n, int m, const int32_t *mult, int check, perm_multi_plan_info_t *out);
 
+/* Measurement probe: the FP64 rate (TFLOP/s, a fused multiply-add counted
+ * as 2 flops) that independent FMA chains sustain on the current device --
+ * the measured counterpart of the spec-sheet FP64 vector peak, for the
+ * roofline fractions of the FP64-bound paths.  Runs about 10 ms of work on
+ * `stream`, synchronizes it, allocates and frees a small device buffer.
+ * PERM_EINVAL for a null pointer, PERM_EDEVICE on a HIP failure. */
+int perm_probe_fp64(double *tflops, void *stream);
+
 /* Device workspace bytes for a batch (host array ns of `count` orders). */
 size_t perm_batch_workspace_bytes(perm_dtype_t dt, int count, const int32_t *ns);
 

@@ -7,3 +7,4 @@
 #include "perm_batch.hip"
 #include "perm_ryser.hip"
 #include "perm_multi.hip"
+#include "perm_probe.hip"

@@ -731,6 +731,33 @@ int perm_solve_multi_async(int n, int m, const int32_t *mult, const perm_c128_t 
     return multi_c128_device(*P, a_dev, lda, result_dev, workspace, ws_bytes, (hipStream_t)stream);
 }
 
+int perm_probe_fp64(double *tflops, void *stream) {
+    if (!tflops) return set_error(PERM_EINVAL, "null pointer");
+    hipStream_t s = (hipStream_t)stream;
+    int dev = 0, cus = 0;
+    MHIP(hipGetDevice(&dev), "hipGetDevice");
+    MHIP(hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev), "hipDeviceGetAttribute");
+    const int blocks = std::max(1, cus) * 16, iters = 1 << 13;  // about 2 ms per launch
+    double *d_out = nullptr;
+    MHIP(hipMalloc(&d_out, (size_t)blocks * sizeof(double)), "hipMalloc (probe)");
+    hipEvent_t e0 = nullptr, e1 = nullptr;
+    hipError_t e = hipEventCreate(&e0);
+    if (e == hipSuccess) e = hipEventCreate(&e1);
+    float ms = 0.f;
+    if (e == hipSuccess) e = launch_probe_fma(d_out, blocks, iters, s);  // warm-up
+    if (e == hipSuccess) e = hipEventRecord(e0, s);
+    for (int r = 0; r < 5 && e == hipSuccess; r++) e = launch_probe_fma(d_out, blocks, iters, s);
+    if (e == hipSuccess) e = hipEventRecord(e1, s);
+    if (e == hipSuccess) e = hipEventSynchronize(e1);
+    if (e == hipSuccess) e = hipEventElapsedTime(&ms, e0, e1);
+    if (e0) (void)hipEventDestroy(e0);
+    if (e1) (void)hipEventDestroy(e1);
+    (void)hipFree(d_out);
+    if (e != hipSuccess) return hip_error(e, "FP64 probe");
+    *tflops = 5.0 * probe_fma_flops(blocks, iters) / (ms * 1e-3) / 1e12;
+    return PERM_OK;
+}
+
 int perm_multi_plan_info(int n, int m, const int32_t *mult, int check, perm_multi_plan_info_t *out) {
     if (!out) return set_error(PERM_EINVAL, "null pointer");
     std::memset(out, 0, sizeof *out);

@@ -52,4 +52,9 @@ hipError_t launch_multi_init_modp(const uint64_t *red, int n, int m, int rp, uin
 hipError_t launch_multi_layer_modp(const uint64_t *prev, uint64_t *next, size_t plane, const uint64_t *red,
                                    const uint64_t *primes, int rp, const MultiLayerArgs &g, hipStream_t s);
 
+// FP64 FMA probe (perm_probe.hip): `blocks` workgroups of independent
+// chains, `iters` steps each; probe_fma_flops gives the flops of one launch.
+hipError_t launch_probe_fma(double *out, int blocks, int iters, hipStream_t s);
+double probe_fma_flops(int blocks, int iters);
+
 }  // namespace permgpu

@@ -51,7 +51,7 @@ EXPORTS = [
     "perm_server_submit", "perm_server_poll", "perm_server_destroy", "perm_tuning_get",
     "perm_tuning_set", "perm_tuning_load", "perm_tuning_save", "perm_tuning_key",
     "perm_profile_enable", "perm_profile_read", "perm_multi_workspace_bytes", "perm_solve_multi",
-    "perm_solve_multi_async", "perm_multi_plan_info",
+    "perm_solve_multi_async", "perm_multi_plan_info", "perm_probe_fp64",
 ]
 
 
@@ -152,6 +152,8 @@ def lib() -> ctypes.CDLL:
         L.perm_solve_multi_async.restype = i32
         L.perm_multi_plan_info.argtypes = [i32, i32, vp, i32, ctypes.POINTER(perm_multi_plan_info_t)]
         L.perm_multi_plan_info.restype = i32
+        L.perm_probe_fp64.argtypes = [ctypes.POINTER(ctypes.c_double), vp]
+        L.perm_probe_fp64.restype = i32
         L.perm_batch_workspace_bytes.argtypes = [i32, i32, vp]
         L.perm_batch_workspace_bytes.restype = sz
         L.perm_solve_batch.argtypes = [i32, i32, vp, vp, vp, vp, vp, sz, vp, u32]
@@ -359,6 +361,13 @@ def perm_multi_plan_info(mult, check: bool = False) -> perm_multi_plan_info_t:
     _check(lib().perm_multi_plan_info(int(t.sum()), t.shape[0], t.ctypes.data, 1 if check else 0,
                                       ctypes.byref(out)))
     return out
+
+
+def perm_probe_fp64(stream=None) -> float:
+    """FP64 TFLOP/s sustained by independent FMA chains (measurement probe)."""
+    v = ctypes.c_double()
+    _check(lib().perm_probe_fp64(ctypes.byref(v), _stream_ptr(stream)))
+    return float(v.value)
 
 
 def perm_batch_workspace_bytes(dtype: int, ns: np.ndarray) -> int:

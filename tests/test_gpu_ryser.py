@@ -161,3 +161,10 @@ def test_ryser_int_n30_bernoulli_equals_store_zechin(P, golden_dir):
     B = inputs.bernoulli01(30, seed=0)
     print("[gpu] ryser int n=30", flush=True)
     assert str(P.perm_ryser(B)) == cfg["value"]
+
+
+def test_fp64_probe_is_plausible(P):
+    """The FMA probe reports a rate between a tenth of and the spec FP64 peak
+    (78.6 TFLOP/s; 1.1x margin for clock variation)."""
+    t = P.perm_probe_fp64()
+    assert 7.86 < t < 1.1 * 78.6, t
