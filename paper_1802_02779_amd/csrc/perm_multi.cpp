@@ -28,7 +28,7 @@ namespace permgpu {
 namespace {
 
 constexpr uint32_t kLowWindow = 1024;        // largest low window wanted (entries)
-constexpr uint64_t kHighMax = 1ull << 22;    // high parts at most
+constexpr uint64_t kHighMax = 1ull << 24;    // high parts at most (the list costs 4 B each)
 constexpr uint64_t kPlanMax = 1ull << 30;    // plan bytes at most
 constexpr uint64_t kSat = ~0ull;
 constexpr uint32_t kNone = 0xffffffffu;
@@ -413,7 +413,7 @@ int check_plan(const MultiPlan &P, uint64_t *checked) {
 
 // ------------------------------------------------------------ plan cache
 // Host plans by multiplicity vector, each with its device copies; at most
-// kPlanCache plans and kDevPlanBytes of device copies, least recently used
+// kPlanCache plans and kDevPlanBytes of device copies, the oldest unused
 // dropped first.
 std::mutex g_plan_mu;
 std::map<std::vector<int32_t>, std::shared_ptr<const MultiPlan>> g_plans;
@@ -422,20 +422,28 @@ size_t g_dev_plan_bytes = 0;
 constexpr size_t kPlanCache = 16;
 constexpr size_t kDevPlanBytes = (size_t)2 << 30;
 
-void drop_oldest_locked() {
-    auto it = g_plans.find(g_plan_order.front());
-    g_plan_order.pop_front();
-    if (it == g_plans.end()) return;
-    if (!it->second->dev.empty()) {
-        // a queued launch may still read the tables
-        (void)hipDeviceSynchronize();
-        for (auto &d : it->second->dev) {
-            (void)hipFree(d.second);
-            g_dev_plan_bytes -= it->second->blob.size() * 4;
+// Drops the least recently built plan that no call is using (only the cache
+// holds it: a call keeps its plan for its whole duration, so no launch can
+// be issued with tables freed here) and that is not `keep`.  Returns false
+// when every plan is in use.
+bool drop_one_locked(const MultiPlan *keep) {
+    for (auto o = g_plan_order.begin(); o != g_plan_order.end(); ++o) {
+        auto it = g_plans.find(*o);
+        if (it == g_plans.end() || it->second.get() == keep || it->second.use_count() > 1) continue;
+        if (!it->second->dev.empty()) {
+            // launches already queued on some stream may still read the tables
+            (void)hipDeviceSynchronize();
+            for (auto &d : it->second->dev) {
+                (void)hipFree(d.second);
+                g_dev_plan_bytes -= it->second->blob.size() * 4;
+            }
+            it->second->dev.clear();
         }
-        it->second->dev.clear();
+        g_plans.erase(it);
+        g_plan_order.erase(o);
+        return true;
     }
-    g_plans.erase(it);
+    return false;
 }
 
 int get_plan(int n, int m, const int32_t *t, std::shared_ptr<const MultiPlan> &out) {
@@ -457,7 +465,8 @@ int get_plan(int n, int m, const int32_t *t, std::shared_ptr<const MultiPlan> &o
         out = it->second;
         return PERM_OK;
     }
-    while (g_plans.size() >= kPlanCache) drop_oldest_locked();
+    while (g_plans.size() >= kPlanCache && drop_one_locked(nullptr)) {
+    }
     g_plans[key] = P;
     g_plan_order.push_back(key);
     out = P;
@@ -475,9 +484,8 @@ int device_plan(const MultiPlan &P, const char **out) {
         return PERM_OK;
     }
     const size_t bytes = P.blob.size() * 4;
-    while (g_dev_plan_bytes + bytes > kDevPlanBytes && g_plan_order.size() > 1 &&
-           g_plans.find(g_plan_order.front())->second.get() != &P)
-        drop_oldest_locked();
+    while (g_dev_plan_bytes + bytes > kDevPlanBytes && drop_one_locked(&P)) {
+    }
     void *ptr = nullptr;
     MHIP(hipMalloc(&ptr, bytes), "hipMalloc (repeated-column plan)");
     const hipError_t e = hipMemcpy(ptr, P.blob.data(), bytes, hipMemcpyHostToDevice);

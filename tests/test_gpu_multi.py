@@ -171,3 +171,15 @@ def test_int_all_ones_largest_layers(P):
     print(f"[gpu] multi int all-ones n={n} m={m}", flush=True)
     assert P.perm_solve_multi(np.ones((n, m), dtype=np.int64), BIG) == math.factorial(n)
     torch.cuda.empty_cache()
+
+
+def test_plan_cache_eviction_on_device(P):
+    """More distinct shapes than the plan cache holds, twice over: plans are
+    dropped (after a device synchronization) and rebuilt; every result stays
+    bitwise equal to the oracle."""
+    shapes = [[2] * k + [1, 3] for k in range(1, 11)] + [[3] * k + [2] for k in range(1, 9)]  # 18 > 16
+    for rep in range(2):
+        for t in shapes:
+            n = sum(t)
+            A = inputs.complex_gaussian(n, seed=n)[:, :len(t)]
+            assert bits(P.perm_solve_multi(A, t)) == bits(native.per_multi_c128(A, t)), (rep, t)

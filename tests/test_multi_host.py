@@ -126,3 +126,13 @@ def test_trivial_orders_without_device(perm):
     assert perm.perm_solve_multi(np.zeros((0, 0), dtype=np.complex128), []) == 1
     assert perm.perm_solve_multi(np.array([[2.5 - 1.0j]]), [1]) == 2.5 - 1.0j
     assert perm.perm_solve_multi(np.array([[-7]], dtype=np.int64), [1]) == -7
+
+
+def test_plan_cache_eviction_rebuilds(perm):
+    """More distinct multiplicity vectors than the cache holds: every query
+    still answers (evicted plans are rebuilt), with the same sizes."""
+    shapes = [[2] * k + [1] * 3 for k in range(1, 19)]  # 18 plans, the cache keeps 16
+    first = [perm.perm_multi_workspace_bytes(perm.PERM_COMPLEX128, t) for t in shapes]
+    again = [perm.perm_multi_workspace_bytes(perm.PERM_COMPLEX128, t) for t in reversed(shapes)]
+    assert first == list(reversed(again))
+    assert all(b > 0 for b in first)
