@@ -189,8 +189,8 @@ int perm_ryser_async(int n, const perm_c128_t *a_dev, int64_t lda, perm_c128_t *
  * Plan: the tables that map every output to its predecessors depend only on
  * mult; the library builds them on the host at the first call for a mult,
  * uploads them once per device into memory it allocates itself, and keeps
- * them (at most 16 plans and 2 GiB of device copies; the least recently
- * built is dropped, after a device synchronization).
+ * them (at most 16 plans and 2 GiB of device copies; beyond that the oldest
+ * plan no call is using is dropped, after a device synchronization).
  * perm_multi_workspace_bytes: device workspace for (n, m, mult): the matrix
  * and the pair of largest layers (for int64 per group of primes); 0 when
  * the arguments are invalid or the layer size or the plan exceeds the limits.
