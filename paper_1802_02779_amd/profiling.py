@@ -44,7 +44,8 @@ def main():
         print(f"\nsum of the step's layer launches: {tot / 1e6:.3f} ms")
 
 
-if __name__ == "__main__" and not (len(sys.argv) > 1 and sys.argv[1] in ("counters", "multi-counters")):
+if __name__ == "__main__" and not (len(sys.argv) > 1 and sys.argv[1] in ("counters", "multi-counters",
+                                                                       "kernel-counters")):
     main()
 
 
@@ -193,6 +194,45 @@ def multi_counters(fetch_db: str, write_db: str, hit_db: str, cmd: str, root: st
             "hbm_bytes_per_solve": int(tf + tw), "fetch_bytes_per_solve": int(tf), "write_bytes_per_solve": int(tw),
             "algorithmic_bytes_per_solve": int(ta), "fetch_factor": ff, "write_factor": wf}
     return "\n".join(lines) + "\n", data
+
+
+def kernel_counters(fetch_db: str, write_db: str, hit_db: str, cmd: str, kernel: str, launches: int,
+                    algorithmic_bytes: int, what: str) -> str:
+    """HBM traffic of the last `launches` dispatches of `kernel` (one solve)
+    from three rocprofv3 --pmc runs, scaled by the 1 GiB copy each run
+    starts with, against the solve's algorithmic bytes."""
+    def load(db):
+        cur = sqlite3.connect(db).cursor()
+        rows = list(cur.execute("select dispatch_id, kernel_name, grid_size, counter_name, value "
+                                "from counters_collection order by dispatch_id"))
+        cal, per = {}, {}
+        for d, k, g, c, v in rows:
+            if "copyBuffer" in k and g == 131072:
+                cal[c] = v
+            if kernel in k:
+                per.setdefault(d, {})[c] = v
+        return cal, [per[d] for d in sorted(per)][-launches:]
+
+    fcal, fl = load(fetch_db)
+    wcal, wl = load(write_db)
+    _, hl = load(hit_db)
+    ff = 1048576.0 / fcal["FETCH_SIZE"]
+    wf = 1048576.0 / wcal["WRITE_SIZE"]
+    tf = sum(x["FETCH_SIZE"] for x in fl) * 1024 * ff
+    tw = sum(x["WRITE_SIZE"] for x in wl) * 1024 * wf
+    hits = sum(x["TCC_HIT_sum"] for x in hl)
+    misses = sum(x["TCC_MISS_sum"] for x in hl)
+    return (f"commands:\n\n    {cmd}\n\nworkload: {what}\n\n"
+            f"calibration (1 GiB device copy): FETCH_SIZE factor {ff:.4f}, WRITE_SIZE factor {wf:.4f}\n\n"
+            f"kernel `{kernel}`, {len(fl)} launches of one solve: fetched {tf / 1e9:.2f} GB, written "
+            f"{tw / 1e9:.2f} GB, algorithmic {algorithmic_bytes / 1e9:.2f} GB, amplification "
+            f"{(tf + tw) / algorithmic_bytes:.2f}, L2 hit rate {hits / max(hits + misses, 1):.3f}\n")
+
+
+if __name__ == "__main__" and len(sys.argv) > 1 and sys.argv[1] == "kernel-counters":
+    # fetch.db write.db hit.db "command" kernel launches algorithmic_bytes "workload"
+    print(kernel_counters(sys.argv[2], sys.argv[3], sys.argv[4], sys.argv[5], sys.argv[6], int(sys.argv[7]),
+                          int(sys.argv[8]), sys.argv[9]))
 
 
 if __name__ == "__main__" and len(sys.argv) > 1 and sys.argv[1] == "multi-counters":
