@@ -354,6 +354,37 @@ def perm_solve_multi_async(n: int, mult, a_dev, lda: int, result_dev, workspace,
                                         _stream_ptr(stream)))
 
 
+def bunched_orientation(row_mult, col_mult) -> bool:
+    """True when perm_solve_bunched compresses the rows (runs on the
+    transpose): the side with fewer count vectors, prod(mult + 1), is the one
+    compressed; ties keep the columns."""
+    r = np.asarray(row_mult, dtype=np.float64)
+    c = np.asarray(col_mult, dtype=np.float64)
+    return float(np.sum(np.log2(r + 1.0))) < float(np.sum(np.log2(c + 1.0))) - 1e-9
+
+
+def perm_solve_bunched(A, row_mult, col_mult, workspace=None, stream=None):
+    """Permanent of the n x n matrix with row i of the r x c matrix A repeated
+    row_mult[i] times and column j repeated col_mult[j] times (sum row_mult =
+    sum col_mult = n): the amplitude, up to the factor
+    1 / sqrt(prod row_mult! prod col_mult!), of bosons that enter r modes and
+    leave c modes with those occupations.  per(A) = per(A^T), so one side is
+    expanded and the other is compressed into count vectors
+    (perm_solve_multi); the side compressed is the one with fewer count
+    vectors (bunched_orientation), which also fixes the fp64 chain, so the
+    complex result is a deterministic function of the inputs."""
+    A = np.asarray(A)
+    rm = np.asarray(row_mult, dtype=np.int64)
+    cm = np.asarray(col_mult, dtype=np.int64)
+    if A.ndim != 2 or A.shape != (rm.shape[0], cm.shape[0]):
+        raise ValueError("one multiplicity per row and per column of A")
+    if int(rm.sum()) != int(cm.sum()):
+        raise ValueError("row and column multiplicities must have the same sum")
+    if bunched_orientation(rm, cm):
+        return perm_solve_multi(np.repeat(A.T, cm, axis=0), rm, workspace=workspace, stream=stream)
+    return perm_solve_multi(np.repeat(A, rm, axis=0), cm, workspace=workspace, stream=stream)
+
+
 def perm_multi_plan_info(mult, check: bool = False) -> perm_multi_plan_info_t:
     """Host-only shape (and, with check, verification) of the plan for mult."""
     t = _mult(mult)

@@ -183,3 +183,23 @@ def test_plan_cache_eviction_on_device(P):
             n = sum(t)
             A = inputs.complex_gaussian(n, seed=n)[:, :len(t)]
             assert bits(P.perm_solve_multi(A, t)) == bits(native.per_multi_c128(A, t)), (rep, t)
+
+
+# ----------------------------------------------------- rows and columns
+@pytest.mark.parametrize("rm,cm", [([2, 1, 3], [1, 1, 1, 1, 1, 1]), ([1] * 6, [3, 3]), ([2, 2], [2, 1, 1]),
+                                   ([4, 1, 1], [2, 2, 2])])
+def test_bunched_rows_and_columns(P, rm, cm):
+    """Repeated rows and columns: exact integers equal eq. (1) on the fully
+    expanded matrix; complex equals the oracle's chain in the orientation the
+    rule picks, bit for bit."""
+    rng = np.random.default_rng(sum(rm) * 10 + len(rm))
+    A = rng.integers(-4, 5, size=(len(rm), len(cm)), dtype=np.int64)
+    full = np.repeat(np.repeat(A, rm, axis=0), cm, axis=1)
+    assert P.perm_solve_bunched(A, rm, cm) == exact.per_definition(full)
+    Z = inputs.complex_gaussian(max(len(rm), len(cm)), seed=7)[:len(rm), :len(cm)]
+    got = P.perm_solve_bunched(Z, rm, cm)
+    if P.bunched_orientation(rm, cm):
+        ref = native.per_multi_c128(np.repeat(Z.T, cm, axis=0), rm)
+    else:
+        ref = native.per_multi_c128(np.repeat(Z, rm, axis=0), cm)
+    assert bits(got) == bits(ref)

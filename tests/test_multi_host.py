@@ -136,3 +136,13 @@ def test_plan_cache_eviction_rebuilds(perm):
     again = [perm.perm_multi_workspace_bytes(perm.PERM_COMPLEX128, t) for t in reversed(shapes)]
     assert first == list(reversed(again))
     assert all(b > 0 for b in first)
+
+
+def test_bunched_orientation_rule(perm):
+    assert not perm.bunched_orientation([1, 1, 1, 1], [2, 2])   # columns compress better
+    assert perm.bunched_orientation([3, 1], [1, 1, 1, 1])       # rows compress better
+    assert not perm.bunched_orientation([2, 1], [2, 1])         # tie keeps the columns
+    with pytest.raises(ValueError):
+        perm.perm_solve_bunched(np.ones((2, 2)), [1, 1], [1, 2])
+    with pytest.raises(ValueError):
+        perm.perm_solve_bunched(np.ones((2, 3)), [1, 2], [1, 2])
