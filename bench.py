@@ -86,7 +86,7 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-extras", action="store_true")
     ap.add_argument("--only", default="",
-                    help="comma list of extra sections to run (n26, ryser, n34, h2h, int30, multi, int10, batch, "
+                    help="comma list of extra sections to run (n26, ryser, n34, h2h, compare, int30, multi, int10, batch, "
                          "serving); "
                          "default: all")
     ap.add_argument("--copy-calibration", action="store_true",
@@ -228,6 +228,8 @@ def extras(perm, inputs, golden, np, torch, log, only=frozenset()):
         _extra_n34(perm, inputs, torch, log, out)
     if want("h2h"):
         _extra_h2h(perm, inputs, out)
+    if want("compare"):
+        _extra_compare(perm, inputs, torch, log, out)
     if want("int30"):
         _extra_int30(perm, inputs, golden, log, out)
     if want("multi"):
@@ -342,6 +344,40 @@ def _extra_n34(perm, inputs, torch, log, out):
                        "ryser_fp64_frac": round(ryser_flops(n) / ry_ms / 1e9 / FP64_PEAK_TFLOPS, 4),
                        "rel_diff": float(abs(r[1] - r[0]) / abs(r[0]))}
     log(f"n=34 complex: Store-zechin {sz_ms:.1f} ms ({ws_gb:.0f} GB), Ryser {ry_ms:.1f} ms")
+
+
+def _extra_compare(perm, inputs, torch, log, out):
+    """The paper's comparison (Table 4: Store-zechin against Ryser's eq. (4)),
+    measured: both methods on the same complex Gaussian matrices, n = 20..34,
+    device-resident, median of 3 after one warm-up call."""
+    C128 = perm.PERM_COMPLEX128
+    rows = []
+    for n in (20, 22, 24, 26, 28, 30, 32, 34):
+        A = inputs.complex_gaussian(n, seed=n)
+        d_a = torch.from_numpy(A).cuda()
+        d_r = torch.zeros(2, dtype=torch.complex128, device="cuda")
+        res = {}
+        for name, wsb, call in (("store_zechin", perm.perm_workspace_bytes, perm.perm_solve_async),
+                                ("ryser", perm.perm_ryser_workspace_bytes, perm.perm_ryser_async)):
+            ws = perm.device_buffer(wsb(C128, n))
+            slot = d_r[0:1] if name == "store_zechin" else d_r[1:2]
+            call(n, d_a, n, slot, ws)
+            torch.cuda.synchronize()
+            ts = []
+            for _ in range(3):
+                t0 = time.perf_counter()
+                call(n, d_a, n, slot, ws)
+                torch.cuda.synchronize()
+                ts.append((time.perf_counter() - t0) * 1000.0)
+            res[name] = sorted(ts)[1]
+            del ws
+            torch.cuda.empty_cache()
+        r = d_r.cpu().numpy()
+        rows.append({"n": n, "store_zechin_ms": round(res["store_zechin"], 3), "ryser_ms": round(res["ryser"], 3),
+                     "ryser_over_sz": round(res["ryser"] / res["store_zechin"], 3),
+                     "rel_diff": float(abs(r[1] - r[0]) / abs(r[0]))})
+        log(f"compare n={n}: Store-zechin {res['store_zechin']:.3f} ms, Ryser {res['ryser']:.3f} ms")
+    out["store_zechin_vs_ryser"] = rows
 
 
 def _extra_h2h(perm, inputs, out):
