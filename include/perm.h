@@ -202,7 +202,9 @@ int perm_ryser_async(int n, const perm_c128_t *a_dev, int64_t lda, perm_c128_t *
  * Errors: PERM_EINVAL for a null pointer, lda < m, a multiplicity below 1 or
  * a sum other than n; PERM_ERANGE for n > PERM_MULTI_N_MAX, every
  * multiplicity 1 with n > PERM_N_MAX, a layer of 2^32 or more count vectors,
- * or (int64) a result beyond PERM_INT_LIMBS limbs or PERM_MAX_PRIMES primes;
+ * a plan beyond its limits (more than 2^24 high parts, or no split whose low
+ * window fits 3072 entries), or (int64) a result beyond PERM_INT_LIMBS limbs
+ * or PERM_MAX_PRIMES primes;
  * PERM_ENOMEM for a workspace below perm_multi_workspace_bytes;
  * PERM_EDEVICE as perm_solve. */
 size_t perm_multi_workspace_bytes(perm_dtype_t dt, int n, int m, const int32_t *mult);
@@ -213,11 +215,11 @@ int perm_solve_multi_async(int n, int m, const int32_t *mult, const perm_c128_t 
 
 /* Shape of the repeated-column plan for (n, m, mult), built on the host (no
  * device needed).  With check != 0 the plan is also verified against the
- * closed-form colex ranking of count vectors: every output of every layer
- * (or, above 2^22 outputs in all, every output of up to 4096-output samples
- * per layer) is unranked, and the rank of each predecessor c - e_j is
- * compared with what the tables give; the number of outputs checked is
- * returned.  PERM_EDEVICE when a check fails (message names the layer and
+ * closed-form colex ranking of count vectors: the tiles of each layer must
+ * cover its ranks exactly once, and every output of every layer (above 2^22
+ * outputs in all: up to about 512 tiles per layer and 64 outputs per tile)
+ * is unranked, and the rank of each predecessor c - e_j is compared with what
+ * the tables give; the number of outputs checked is returned.  PERM_EDEVICE when a check fails (message names the layer and
  * rank).  With every mult[j] = 1 no plan exists (the subset path runs):
  * fields are zero except states = 2^n.  */
 typedef struct {
