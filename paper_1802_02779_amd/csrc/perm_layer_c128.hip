@@ -66,9 +66,23 @@ __device__ void layer_c128_thin(const double2 *__restrict__ prev, double2 *__res
             if (i >= 2) base_h += s_bin[h * kBinomDim + kp + i - 1];
         }
     }
+    // terms in groups of four: the group's loads are issued before its FMAs
+    // (one memory latency per group, not per term); the FMA order is the
+    // chain's
     double re = 0.0, im = 0.0;
     const uint32_t *lt = g_lowtab + args.t_low_off[g];
-    for (int p = 0; p < kp; p++) {
+    int p = 0;
+    for (; p + 4 <= kp; p += 4) {
+        uint32_t e[4];
+        double2 w[4];
+#pragma unroll
+        for (int u = 0; u < 4; u++) e[u] = lt[(uint32_t)(p + u) * ck + r];
+#pragma unroll
+        for (int u = 0; u < 4; u++) w[u] = prev[base_low + (e[u] & 0xffffu)];
+#pragma unroll
+        for (int u = 0; u < 4; u++) cfma(re, im, s_arow[e[u] >> 16], w[u]);
+    }
+    for (; p < kp; p++) {
         const uint32_t e = lt[(uint32_t)p * ck + r];
         cfma(re, im, s_arow[e >> 16], prev[base_low + (e & 0xffffu)]);
     }
@@ -77,12 +91,30 @@ __device__ void layer_c128_thin(const double2 *__restrict__ prev, double2 *__res
     uint32_t b = T;
     int q = 1, hprev = 0;
     while (b) {
-        const int h = __ffs(b) - 1 + t;
-        b &= b - 1;
-        if (q > 1) base_h = base_h + s_bin[hprev * kBinomDim + kp + q - 1] - s_bin[h * kBinomDim + kp + q - 1];
-        cfma(re, im, s_arow[h], prev[base_h + r]);
-        hprev = h;
-        q++;
+        int hh[4];
+        uint32_t bb[4];
+        int cnt = 0;
+#pragma unroll
+        for (int u = 0; u < 4; u++) {
+            if (b) {
+                const int h = __ffs(b) - 1 + t;
+                b &= b - 1;
+                if (q > 1)
+                    base_h = base_h + s_bin[hprev * kBinomDim + kp + q - 1] - s_bin[h * kBinomDim + kp + q - 1];
+                hh[u] = h;
+                bb[u] = base_h;
+                hprev = h;
+                q++;
+                cnt++;
+            }
+        }
+        double2 w[4];
+#pragma unroll
+        for (int u = 0; u < 4; u++)
+            if (u < cnt) w[u] = prev[bb[u] + r];
+#pragma unroll
+        for (int u = 0; u < 4; u++)
+            if (u < cnt) cfma(re, im, s_arow[hh[u]], w[u]);
     }
     double2 *out = next + base_out + r;
     if (args.nt_store) {
