@@ -130,7 +130,7 @@ def multi_source_hash(root: str) -> str:
     import os
     h = hashlib.sha256()
     csrc = os.path.join(root, "paper_1802_02779_amd", "csrc")
-    for f in ("perm_multi.hip", "perm_multi.cpp", "perm_multi.h", "perm_layer_c128.hip"):
+    for f in ("perm_multi.hip", "perm_multi.cpp", "perm_multi.h"):
         with open(os.path.join(csrc, f), "rb") as fh:
             h.update(fh.read())
     return h.hexdigest()[:16]
