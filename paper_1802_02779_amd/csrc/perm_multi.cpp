@@ -234,6 +234,9 @@ int build_plan(int n, int m, const int32_t *t, MultiPlan &P) {
     return PERM_OK;
 }
 
+// Launch arguments of layer k.  The runs of |h| groups at either end of the
+// layer whose tiles have at most kMultiThin outputs (WL[k - |h|]) are its
+// thin tiles.
 MultiLayerArgs layer_args(const MultiPlan &P, const char *d_blob, int k) {
     MultiLayerArgs g;
     const uint32_t *w = (const uint32_t *)d_blob;
@@ -247,6 +250,16 @@ MultiLayerArgs layer_args(const MultiPlan &P, const char *d_blob, int k) {
     const int qlo = std::max(0, k - P.SL), qhi = std::min(k, P.SH);
     g.tile0 = P.qoff[qlo];
     g.ntiles = qlo <= qhi ? P.qoff[qhi + 1] - P.qoff[qlo] : 0;
+    g.thin_lo = 0;
+    g.thin_hi = g.ntiles;
+    if (qlo <= qhi) {
+        int a = qlo, b = qhi;
+        while (a <= qhi && P.WL[k - a] <= (uint32_t)kMultiThin) a++;
+        while (b >= a && P.WL[k - b] <= (uint32_t)kMultiThin) b--;
+        g.thin_lo = P.qoff[a] - g.tile0;
+        g.thin_hi = P.qoff[b + 1] - g.tile0;
+    }
+    g.thin_wg = (g.thin_lo + (g.ntiles - g.thin_hi) + kMultiBlock / 64 - 1) / (kMultiBlock / 64);
     g.n = P.n;
     g.m = P.m;
     g.L = P.L;
@@ -344,6 +357,9 @@ int check_plan(const MultiPlan &P, uint64_t *checked) {
     uint64_t done = 0;
     for (int k = 2; k <= P.n; k++) {
         const MultiLayerArgs g = layer_args(P, (const char *)B, k);
+        if (g.thin_lo > g.thin_hi || g.thin_hi > g.ntiles)
+            return set_error(PERM_EDEVICE, "plan check: layer %d thin split %u..%u of %u tiles", k, g.thin_lo,
+                             g.thin_hi, g.ntiles);
         // the tiles of a layer cover its ranks exactly once
         uint64_t covered = 0;
         const uint32_t tstep = (full || g.ntiles <= 512) ? 1 : g.ntiles / 512;
@@ -352,6 +368,8 @@ int check_plan(const MultiPlan &P, uint64_t *checked) {
             if ((int)T.kp < 0 || (int)T.kp > P.SL)
                 return set_error(PERM_EDEVICE, "plan check: layer %d tile %u low sum %d", k, bi, (int)T.kp);
             const uint32_t nout = P.WL[T.kp];
+            if ((bi < g.thin_lo || bi >= g.thin_hi) && nout > (uint32_t)kMultiThin)
+                return set_error(PERM_EDEVICE, "plan check: layer %d thin tile %u has %u outputs", k, bi, nout);
             covered += nout;
             if (bi % tstep != 0 && bi + 1 != g.ntiles) continue;
             if ((uint64_t)T.base_out + nout > P.size[k])

@@ -11,6 +11,7 @@ namespace permgpu {
 constexpr int kMultiBlock = 256;     // threads per tile workgroup
 constexpr int kMultiMMax = 64;       // distinct columns
 constexpr int kMultiWinMax = 3072;   // largest low window staged in LDS (entries)
+constexpr int kMultiThin = 64;       // tiles with at most this many outputs take one wave each
 
 // Layer k of the sweep over count vectors c with |c| = k, in colex order
 // (last column most significant).  Columns 0..L-1 are "low", L..m-1 "high".
@@ -27,7 +28,9 @@ constexpr int kMultiWinMax = 3072;   // largest low window staged in LDS (entrie
 //            [i][r] = rank of (low part r) - e_i among the low parts of sum
 //            kp - 1, or 0xffff when that low part has no copy of column i;
 //   WL       low parts per sum.
-// Tile b of layer k is hlist[tile0 + b].
+// Tile b of layer k is hlist[tile0 + b].  Tiles [0, thin_lo) and
+// [thin_hi, ntiles) are thin (few outputs): thin_wg workgroups take four of
+// them each, one per wave; the tiles between take a workgroup each.
 struct MultiLayerArgs {
     const uint32_t *G;
     const uint32_t *hlist;
@@ -38,6 +41,7 @@ struct MultiLayerArgs {
     const uint32_t *WL;
     uint32_t tile0;
     uint32_t ntiles;
+    uint32_t thin_lo, thin_hi, thin_wg;
     int n, m, L, SL, k, tmax1;
 };
 

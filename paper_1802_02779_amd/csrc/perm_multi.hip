@@ -58,11 +58,11 @@ __device__ __forceinline__ uint32_t wave_incl_scan(uint32_t v) {
 
 // Workgroup -> tile: runs of kMultiXcdRun consecutive tiles on one XCD
 // (workgroups are dealt to the 8 XCDs in turn), so tiles that read the same
-// predecessor windows share that XCD's L2; 0 keeps the identity.
+// predecessor windows share that XCD's L2; 0 keeps the identity.  b is the
+// workgroup's index among the `ntiles` workgroups of its kind.
 constexpr uint32_t kMultiXcdRun = 64;
 
-__device__ __forceinline__ uint32_t multi_tile_index(uint32_t ntiles) {
-    const uint32_t b = blockIdx.x;
+__device__ __forceinline__ uint32_t multi_tile_index(uint32_t b, uint32_t ntiles) {
     if (kMultiXcdRun == 0) return b;
     const uint32_t span = 8u * kMultiXcdRun;
     if (b >= (ntiles / span) * span) return b;
@@ -70,57 +70,102 @@ __device__ __forceinline__ uint32_t multi_tile_index(uint32_t ntiles) {
     return (b - r) + (r % 8u) * kMultiXcdRun + r / 8u;
 }
 
-// Decodes tile blockIdx.x of layer k and its predecessor tiles into t, in
-// wave 0 with one lane per high column j (prefix sums by shuffles):
+// Decodes tile `tile` of layer k and its predecessor tiles into t, in one
+// wave (lane = 0..63, all lanes present) with one lane per high column j
+// (prefix sums by shuffles):
 //   P_j  = kp + h_L + ... + h_j,
 //   base = sum_j G_j(P_j, h_j)                       (this tile, layer k),
 //   low  = sum_j G_j(P_j - 1, h_j)                   (tile h, layer k-1, low sum kp-1),
 //   win_j = sum_{i<j} G_i(P_i, h_i) + G_j(P_j - 1, h_j - 1)
 //         + sum_{i>j} G_i(P_i - 1, h_i)               (tile h - e_j, layer k-1).
-// Every thread of the workgroup must call it (it ends with a barrier).
-__device__ __forceinline__ void multi_tile(const MultiLayerArgs &g, MultiTileLds &t) {
-    const int tid = threadIdx.x;
-    if (tid < 64) {
-        const int mh = g.m - g.L;
-        const bool act = tid < mh;
-        const uint32_t x = g.hlist[g.tile0 + multi_tile_index(g.ntiles)];
-        const uint32_t h = act ? (x / g.hstride[tid]) % g.hradix[tid] : 0u;
-        const uint32_t ph = wave_incl_scan(h);
-        const int kp = g.k - (int)__shfl(ph, 63);
-        const int P = kp + (int)ph;
-        const uint32_t *Gj = g.G + (size_t)(act ? tid : 0) * (g.n + 1) * g.tmax1;
-        const uint32_t a = act ? Gj[(size_t)P * g.tmax1 + h] : 0u;
-        const uint32_t b = (act && P >= 1) ? Gj[(size_t)(P - 1) * g.tmax1 + h] : 0u;
-        const uint32_t c = (act && h > 0) ? Gj[(size_t)(P - 1) * g.tmax1 + h - 1] : 0u;
-        const uint32_t pa = wave_incl_scan(a), pb = wave_incl_scan(b);
-        const uint32_t tot_a = __shfl(pa, 63), tot_b = __shfl(pb, 63);
-        const uint64_t has = __ballot(act && h > 0);
-        if (act && h > 0) {
-            const int slot = __popcll(has & ((1ull << tid) - 1));
-            t.wbase[slot] = (pa - a) + c + (tot_b - pb);
-            t.wcol[slot] = (uint32_t)(g.L + tid);
-        }
-        if (tid == 0) {
-            t.base_out = tot_a;
-            t.kp = (uint32_t)kp;
-            t.low_base = tot_b;
-            t.nh = (uint32_t)__popcll(has);
-        }
+// The caller makes t visible to the readers with a barrier.
+__device__ __forceinline__ void decode_tile(const MultiLayerArgs &g, uint32_t tile, MultiTileLds &t, int lane) {
+    const int mh = g.m - g.L;
+    const bool act = lane < mh;
+    const uint32_t x = g.hlist[g.tile0 + tile];
+    const uint32_t h = act ? (x / g.hstride[lane]) % g.hradix[lane] : 0u;
+    const uint32_t ph = wave_incl_scan(h);
+    const int kp = g.k - (int)__shfl(ph, 63);
+    const int P = kp + (int)ph;
+    const uint32_t *Gj = g.G + (size_t)(act ? lane : 0) * (g.n + 1) * g.tmax1;
+    const uint32_t a = act ? Gj[(size_t)P * g.tmax1 + h] : 0u;
+    const uint32_t b = (act && P >= 1) ? Gj[(size_t)(P - 1) * g.tmax1 + h] : 0u;
+    const uint32_t c = (act && h > 0) ? Gj[(size_t)(P - 1) * g.tmax1 + h - 1] : 0u;
+    const uint32_t pa = wave_incl_scan(a), pb = wave_incl_scan(b);
+    const uint32_t tot_a = __shfl(pa, 63), tot_b = __shfl(pb, 63);
+    const uint64_t has = __ballot(act && h > 0);
+    if (act && h > 0) {
+        const int slot = __popcll(has & ((1ull << lane) - 1));
+        t.wbase[slot] = (pa - a) + c + (tot_b - pb);
+        t.wcol[slot] = (uint32_t)(g.L + lane);
     }
-    __syncthreads();
+    if (lane == 0) {
+        t.base_out = tot_a;
+        t.kp = (uint32_t)kp;
+        t.low_base = tot_b;
+        t.nh = (uint32_t)__popcll(has);
+    }
 }
 
+// The high terms of output r, in column order after the low ones, four
+// windows' loads in flight.
+__device__ __forceinline__ void multi_high_c128(double &re, double &im, const double2 *__restrict__ prev,
+                                                const double2 *s_row, const MultiTileLds &t, uint32_t r) {
+    const uint32_t nh = t.nh;
+    uint32_t w = 0;
+    for (; w + 4 <= nh; w += 4) {
+        double2 p[4];
+#pragma unroll
+        for (int u = 0; u < 4; u++) p[u] = prev[t.wbase[w + u] + r];
+#pragma unroll
+        for (int u = 0; u < 4; u++) cfma(re, im, s_row[t.wcol[w + u]], p[u]);
+    }
+    for (; w < nh; w++) cfma(re, im, s_row[t.wcol[w]], prev[t.wbase[w] + r]);
+}
+
+// Workgroups [0, thin_wg) take four thin tiles each, one per wave, their low
+// predecessors gathered straight from the previous layer (a thin tile's
+// window is a few cache lines); the others take one tile each with its low
+// window staged in LDS.  Both keep the canonical chain: low columns first,
+// then high columns, in column order.
 __global__ __launch_bounds__(kMultiBlock) void k_multi_layer_c128(const double2 *__restrict__ prev,
                                                                  double2 *__restrict__ next,
                                                                  const double2 *__restrict__ row,
                                                                  const MultiLayerArgs g) {
     extern __shared__ double2 s_win[];
     __shared__ double2 s_row[kMultiMMax];
-    __shared__ MultiTileLds t;
+    __shared__ MultiTileLds tl[kMultiBlock / 64];
     const int tid = threadIdx.x;
     for (int j = tid; j < g.m; j += kMultiBlock) s_row[j] = row[j];
-    multi_tile(g, t);
-    const uint32_t kp = t.kp, base_out = t.base_out, nh = t.nh;
+    const uint32_t b = blockIdx.x;
+    if (b < g.thin_wg) {
+        const int wv = tid >> 6, lane = tid & 63;
+        const uint32_t i = b * (kMultiBlock / 64) + (uint32_t)wv;
+        const bool valid = i < g.thin_lo + (g.ntiles - g.thin_hi);
+        if (valid) decode_tile(g, i < g.thin_lo ? i : g.thin_hi + (i - g.thin_lo), tl[wv], lane);
+        __syncthreads();
+        if (!valid) return;
+        const MultiTileLds &t = tl[wv];
+        const uint32_t kp = t.kp, nout = g.WL[kp];
+        const uint16_t *lp = g.lp16 + g.kpoff[kp];
+        const double2 *low = prev + t.low_base;
+        for (uint32_t r = lane; r < nout; r += 64) {
+            double re = 0.0, im = 0.0;
+            if (kp >= 1) {
+                for (int c = 0; c < g.L; c++) {
+                    const uint32_t q = lp[(size_t)c * nout + r];
+                    if (q != 0xffffu) cfma(re, im, s_row[c], low[q]);
+                }
+            }
+            multi_high_c128(re, im, prev, s_row, t, r);
+            next[t.base_out + r] = make_double2(re, im);
+        }
+        return;
+    }
+    MultiTileLds &t = tl[0];
+    if (tid < 64) decode_tile(g, g.thin_lo + multi_tile_index(b - g.thin_wg, g.thin_hi - g.thin_lo), t, tid);
+    __syncthreads();
+    const uint32_t kp = t.kp, base_out = t.base_out;
     if (kp >= 1) {
         const uint32_t nwin = g.WL[kp - 1];
         const double2 *src = prev + t.low_base;
@@ -137,23 +182,19 @@ __global__ __launch_bounds__(kMultiBlock) void k_multi_layer_c128(const double2 
                 if (q != 0xffffu) cfma(re, im, s_row[i], s_win[q]);
             }
         }
-        uint32_t w = 0;
-        for (; w + 4 <= nh; w += 4) {
-            double2 p[4];
-#pragma unroll
-            for (int u = 0; u < 4; u++) p[u] = prev[t.wbase[w + u] + r];
-#pragma unroll
-            for (int u = 0; u < 4; u++) cfma(re, im, s_row[t.wcol[w + u]], p[u]);
-        }
-        for (; w < nh; w++) cfma(re, im, s_row[t.wcol[w]], prev[t.wbase[w] + r]);
+        multi_high_c128(re, im, prev, s_row, t, r);
         next[base_out + r] = make_double2(re, im);
     }
 }
 
 hipError_t launch_multi_layer_c128(const void *prev, void *next, const void *row, const MultiLayerArgs &g,
                                    uint32_t max_window, hipStream_t s) {
-    if (max_window > (uint32_t)kMultiWinMax) return hipErrorInvalidValue;
-    hipLaunchKernelGGL(k_multi_layer_c128, dim3(g.ntiles), dim3(kMultiBlock), (size_t)max_window * 16, s,
+    if (max_window > (uint32_t)kMultiWinMax || g.thin_lo > g.thin_hi || g.thin_hi > g.ntiles ||
+        (uint64_t)g.thin_wg * (kMultiBlock / 64) < (uint64_t)g.thin_lo + (g.ntiles - g.thin_hi))
+        return hipErrorInvalidValue;
+    const uint32_t grid = g.thin_wg + (g.thin_hi - g.thin_lo);
+    if (grid == 0) return hipSuccess;
+    hipLaunchKernelGGL(k_multi_layer_c128, dim3(grid), dim3(kMultiBlock), (size_t)max_window * 16, s,
                        (const double2 *)prev, (double2 *)next, (const double2 *)row, g);
     return hipGetLastError();
 }
@@ -188,57 +229,88 @@ hipError_t launch_multi_init_modp(const uint64_t *red, int n, int m, int rp, uin
 // products below 2^122 exactly in 128 bits, then one fold.  Predecessors
 // are read from HBM / cache directly (RP planes rarely fit one LDS window).
 template <int RP>
+__device__ __forceinline__ void multi_output_modp(const uint64_t *__restrict__ prev, uint64_t *__restrict__ next,
+                                                  size_t plane, const uint64_t (*s_row)[kMultiMMax],
+                                                  const uint64_t *__restrict__ primes, const MultiLayerArgs &g,
+                                                  const MultiTileLds &t, const uint16_t *lp, uint32_t nout,
+                                                  uint32_t rr) {
+    u128 acc[RP];
+#pragma unroll
+    for (int r = 0; r < RP; r++) acc[r] = 0;
+    if (t.kp >= 1) {
+        for (int i = 0; i < g.L; i++) {
+            const uint32_t q = lp[(size_t)i * nout + rr];
+            if (q == 0xffffu) continue;
+#pragma unroll
+            for (int r = 0; r < RP; r++) acc[r] += (u128)s_row[r][i] * prev[(size_t)r * plane + t.low_base + q];
+        }
+    }
+    for (uint32_t w = 0; w < t.nh; w++) {
+        const uint32_t col = t.wcol[w], b = t.wbase[w];
+#pragma unroll
+        for (int r = 0; r < RP; r++) acc[r] += (u128)s_row[r][col] * prev[(size_t)r * plane + b + rr];
+    }
+#pragma unroll
+    for (int r = 0; r < RP; r++) next[(size_t)r * plane + t.base_out + rr] = fold61(acc[r], primes[r]);
+}
+
+// The same split into thin tiles (one per wave) and workgroup tiles as the
+// complex sweep.
+template <int RP>
 __global__ __launch_bounds__(kMultiBlock) void k_multi_layer_modp(const uint64_t *__restrict__ prev,
                                                                  uint64_t *__restrict__ next, size_t plane,
                                                                  const uint64_t *__restrict__ red,
                                                                  const uint64_t *__restrict__ primes,
                                                                  const MultiLayerArgs g) {
     __shared__ uint64_t s_row[RP][kMultiMMax];
-    __shared__ MultiTileLds t;
+    __shared__ MultiTileLds tl[kMultiBlock / 64];
     const int tid = threadIdx.x;
     for (int e = tid; e < RP * g.m; e += kMultiBlock) {
         const int r = e / g.m, j = e - r * g.m;
         s_row[r][j] = red[(size_t)r * g.n * g.m + (size_t)(g.k - 1) * g.m + j];
     }
-    multi_tile(g, t);
-    const uint32_t kp = t.kp, base_out = t.base_out, nh = t.nh, low = t.low_base;
-    const uint32_t nout = g.WL[kp];
-    const uint16_t *lp = g.lp16 + g.kpoff[kp];
-    for (uint32_t rr = tid; rr < nout; rr += kMultiBlock) {
-        u128 acc[RP];
-#pragma unroll
-        for (int r = 0; r < RP; r++) acc[r] = 0;
-        if (kp >= 1) {
-            for (int i = 0; i < g.L; i++) {
-                const uint32_t q = lp[(size_t)i * nout + rr];
-                if (q == 0xffffu) continue;
-#pragma unroll
-                for (int r = 0; r < RP; r++) acc[r] += (u128)s_row[r][i] * prev[(size_t)r * plane + low + q];
-            }
-        }
-        for (uint32_t w = 0; w < nh; w++) {
-            const uint32_t col = t.wcol[w], b = t.wbase[w];
-#pragma unroll
-            for (int r = 0; r < RP; r++) acc[r] += (u128)s_row[r][col] * prev[(size_t)r * plane + b + rr];
-        }
-#pragma unroll
-        for (int r = 0; r < RP; r++) next[(size_t)r * plane + base_out + rr] = fold61(acc[r], primes[r]);
+    const uint32_t b = blockIdx.x;
+    if (b < g.thin_wg) {
+        const int wv = tid >> 6, lane = tid & 63;
+        const uint32_t i = b * (kMultiBlock / 64) + (uint32_t)wv;
+        const bool valid = i < g.thin_lo + (g.ntiles - g.thin_hi);
+        if (valid) decode_tile(g, i < g.thin_lo ? i : g.thin_hi + (i - g.thin_lo), tl[wv], lane);
+        __syncthreads();
+        if (!valid) return;
+        const MultiTileLds &t = tl[wv];
+        const uint32_t nout = g.WL[t.kp];
+        const uint16_t *lp = g.lp16 + g.kpoff[t.kp];
+        for (uint32_t rr = lane; rr < nout; rr += 64)
+            multi_output_modp<RP>(prev, next, plane, s_row, primes, g, t, lp, nout, rr);
+        return;
     }
+    if (tid < 64) decode_tile(g, g.thin_lo + multi_tile_index(b - g.thin_wg, g.thin_hi - g.thin_lo), tl[0], tid);
+    __syncthreads();
+    const MultiTileLds &t = tl[0];
+    const uint32_t nout = g.WL[t.kp];
+    const uint16_t *lp = g.lp16 + g.kpoff[t.kp];
+    for (uint32_t rr = tid; rr < nout; rr += kMultiBlock)
+        multi_output_modp<RP>(prev, next, plane, s_row, primes, g, t, lp, nout, rr);
 }
 
 hipError_t launch_multi_layer_modp(const uint64_t *prev, uint64_t *next, size_t plane, const uint64_t *red,
                                    const uint64_t *primes, int rp, const MultiLayerArgs &g, hipStream_t s) {
+    if (g.thin_lo > g.thin_hi || g.thin_hi > g.ntiles ||
+        (uint64_t)g.thin_wg * (kMultiBlock / 64) < (uint64_t)g.thin_lo + (g.ntiles - g.thin_hi))
+        return hipErrorInvalidValue;
+    const uint32_t grid = g.thin_wg + (g.thin_hi - g.thin_lo);
+    if (grid == 0) return hipSuccess;
     switch (rp) {
     case 1:
-        hipLaunchKernelGGL(k_multi_layer_modp<1>, dim3(g.ntiles), dim3(kMultiBlock), 0, s, prev, next, plane, red,
+        hipLaunchKernelGGL(k_multi_layer_modp<1>, dim3(grid), dim3(kMultiBlock), 0, s, prev, next, plane, red,
                            primes, g);
         break;
     case 2:
-        hipLaunchKernelGGL(k_multi_layer_modp<2>, dim3(g.ntiles), dim3(kMultiBlock), 0, s, prev, next, plane, red,
+        hipLaunchKernelGGL(k_multi_layer_modp<2>, dim3(grid), dim3(kMultiBlock), 0, s, prev, next, plane, red,
                            primes, g);
         break;
     case 3:
-        hipLaunchKernelGGL(k_multi_layer_modp<3>, dim3(g.ntiles), dim3(kMultiBlock), 0, s, prev, next, plane, red,
+        hipLaunchKernelGGL(k_multi_layer_modp<3>, dim3(grid), dim3(kMultiBlock), 0, s, prev, next, plane, red,
                            primes, g);
         break;
     default:

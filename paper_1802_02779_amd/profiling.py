@@ -14,7 +14,8 @@ import sys
 
 def main():
     db, cmd = sys.argv[1], sys.argv[2]
-    n = int(sys.argv[3]) if len(sys.argv) > 3 else 28
+    multi = len(sys.argv) > 3 and sys.argv[3] == "multi"
+    n = int(sys.argv[3]) if len(sys.argv) > 3 and not multi else 28
     cur = sqlite3.connect(db).cursor()
     print(f"command: `{cmd}`\n")
     print("| kernel | calls | total us | average us | % |")
@@ -30,6 +31,9 @@ def main():
         print("|---|---|---|---|")
         for name, d, g, wg in longest:
             print(f"| {re.sub(r'[(].*', '', name)} | {d / 1000:.1f} | {g // max(wg, 1)} | {wg} |")
+    if multi:
+        multi_layers(cur)
+        return
     rows = list(cur.execute("select duration, grid_x, workgroup_x, lds_size from kernels "
                             "where name like '%k_layer_c128%' order by start"))
     if len(rows) >= n - 1:
@@ -44,9 +48,29 @@ def main():
         print(f"\nsum of the step's layer launches: {tot / 1e6:.3f} ms")
 
 
-if __name__ == "__main__" and not (len(sys.argv) > 1 and sys.argv[1] in ("counters", "multi-counters",
-                                                                       "kernel-counters")):
-    main()
+def multi_layers(cur):
+    """Per-layer durations of the last complex solve of the repeated-column
+    sweep over the 40-photon workload (20 detectors, seed 0)."""
+    import os
+    root = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+    sys.path.insert(0, root)
+    from paper_1802_02779_amd import inputs
+    t = inputs.bunched_pattern(40, 20, 0).tolist()
+    W = multi_layer_sizes(t)
+    n = sum(t)
+    rows = list(cur.execute("select duration, grid_x, workgroup_x from kernels "
+                            "where name like '%k_multi_layer_c128%' order by start"))
+    if len(rows) < n - 1:
+        return
+    print(f"\nlast complex solve, repeated columns {t} (n = {n}):\n")
+    print("| layer k | us | workgroups | count vectors | algorithmic GB/s |")
+    print("|---|---|---|---|---|")
+    tot = 0
+    for k, (d, g, wg) in zip(range(2, n + 1), rows[-(n - 1):]):
+        by = 16 * (W[k - 1] + W[k])
+        tot += d
+        print(f"| {k} | {d / 1000:.1f} | {g // wg} | {W[k]} | {by / d:.0f} |")
+    print(f"\nsum of the solve's layer launches: {tot / 1e6:.3f} ms")
 
 
 def source_hash(root: str, n: int = 28) -> str:
@@ -257,3 +281,8 @@ if __name__ == "__main__" and len(sys.argv) > 1 and sys.argv[1] == "counters":
     print(md)
     with open(os.path.join(root, "profiles", "layer_c128_n28_counters.json"), "w") as f:
         json.dump(data, f, indent=1)
+
+
+if __name__ == "__main__" and not (len(sys.argv) > 1 and sys.argv[1] in ("counters", "multi-counters",
+                                                                       "kernel-counters")):
+    main()
