@@ -123,8 +123,10 @@ int perm_solve_async(int n, const perm_c128_t *a_dev, int64_t lda, perm_c128_t *
 
 #define PERM_BATCH_SYNC 1u   /* wait for completion before returning */
 #define PERM_BATCH_GRAPH 2u  /* launch through a captured HIP graph (replayed on repeat calls) */
-#define PERM_BATCH_REUSE 4u  /* ns/offsets are the same as in the previous call with this
-                              * workspace: skip rebuilding and re-uploading the work list */
+#define PERM_BATCH_REUSE 4u  /* with PERM_BATCH_GRAPH: ns/offsets are the same as in the
+                              * previous call with this workspace, so the captured graph is
+                              * replayed without rebuilding or re-uploading the work list
+                              * (ignored without PERM_BATCH_GRAPH) */
 
 /* ----------------------------------------------------------- Ryser --- */
 

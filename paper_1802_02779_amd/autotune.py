@@ -94,7 +94,7 @@ def tune_layer(perm, inputs, torch, n: int, log=_log, reps: int = 3):
     return best
 
 
-def tune_batch(perm, inputs, torch, n: int, count: int = 1 << 15, log=_log, reps: int = 5):
+def tune_batch(perm, inputs, torch, n: int, count: int = 1 << 16, log=_log, reps: int = 7):
     C = perm.PERM_COMPLEX128
     U = inputs.haar_unitary(64, seed=2018)
     b = inputs.submatrix_batch(U, count, n, n, seed=n)
@@ -105,7 +105,12 @@ def tune_batch(perm, inputs, torch, n: int, count: int = 1 << 15, log=_log, reps
     cand = perm.perm_tuning_t.from_buffer_copy(base)
     cand.batch_group[n] = 0
     perm.perm_tuning_set(cand)
-    run = lambda: perm.perm_solve_batch(C, b.ns, b.offsets, d_mats, d_out, ws)  # noqa: E731
+    # each candidate plans its work list and captures its graph once (with the
+    # tuning in force), then the graph replay alone is timed
+    G, R, Y = perm.PERM_BATCH_GRAPH, perm.PERM_BATCH_REUSE, perm.PERM_BATCH_SYNC
+    plan = lambda: perm.perm_solve_batch(C, b.ns, b.offsets, d_mats, d_out, ws, flags=G | Y)  # noqa: E731
+    run = lambda: perm.perm_solve_batch(C, b.ns, b.offsets, d_mats, d_out, ws, flags=G | R | Y)  # noqa: E731
+    plan()
     ref_ms = _time_ms(run, reps, torch.cuda.synchronize)
     ref = d_out.cpu().numpy().view(np.uint64).copy()
     best = (ref_ms, 0)
@@ -113,6 +118,7 @@ def tune_batch(perm, inputs, torch, n: int, count: int = 1 << 15, log=_log, reps
         cand = perm.perm_tuning_t.from_buffer_copy(base)
         cand.batch_group[n] = g
         perm.perm_tuning_set(cand)
+        plan()
         ms = _time_ms(run, reps, torch.cuda.synchronize)
         if not (d_out.cpu().numpy().view(np.uint64) == ref).all():
             log(f"  batch n={n} group={g}: result differs, rejected")

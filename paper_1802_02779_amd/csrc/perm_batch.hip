@@ -101,8 +101,8 @@ constexpr int cbinom(int n, int k) {
 }
 
 // One chunk of matrices of order N.  Layer by layer, each lane computes whole
-// stored values F(S) with the fixed chain over columns in ascending order;
-// the column loop is unrolled and the row of A is held in registers.
+// stored values F(S) with the fixed chain over the columns of S in ascending
+// order (k is a compile-time constant in each unrolled layer).
 // mi is the result index of this thread's matrix (read with the prefetch).
 template <int N>
 __device__ __forceinline__ void batch_chunk_c128(const BatchChunk ch, int nmax, const uint16_t *s_masks, double2 *area,
@@ -120,31 +120,33 @@ __device__ __forceinline__ void batch_chunk_c128(const BatchChunk ch, int nmax, 
     for (int k = 2; k <= N; k++) {
         if (active) {
             const uint16_t *ml = s_masks + mask_block(kBatchNMax, k);
-            double2 a[N];
-#pragma unroll
-            for (int j = 0; j < N; j++) a[j] = mat[(k - 1) * N + j];
+            // row k-1 of A, read per term at the lane's own column
+            const double2 *rowk = mat + (k - 1) * N;
             const int cnt = cbinom(N, k);
-            // the mask of the lane's next entry is read one round ahead, and
-            // all predecessor loads go to distinct registers before the chain
-            // starts, so each round waits for LDS once
             uint32_t Sn = lane < cnt ? ml[lane] : 0u;
             for (int i = lane; i < cnt; i += G) {
                 const uint32_t S = Sn;
                 if (i + G < cnt) Sn = ml[i + G];
                 const double2 *t0 = tab + cpos<N>(S);
-                // a column outside S contributes no term
-                double2 p[N];
+                // the k columns of S, lowest first (every lane of the layer has
+                // exactly k): each term's predecessor and coefficient are read
+                // into distinct registers before the chain starts, so a round
+                // waits for LDS once and issues no masked-off work
+                double2 p[N], c[N];
+                uint32_t Sr = S;
 #pragma unroll
-                for (int j = 0; j < N; j++)
-                    if ((S >> j) & 1u) p[j] = t0[1u << j];
-                double re = 0.0, im = 0.0;
-#pragma unroll
-                for (int j = 0; j < N; j++) {
-                    if ((S >> j) & 1u) {
-                        asm volatile("");  // keep this a masked block rather than selects
-                        bcfma(re, im, a[j], p[j]);
+                for (int u = 0; u < N; u++) {
+                    if (u < k) {
+                        const uint32_t j = (uint32_t)__builtin_ctz(Sr);
+                        Sr &= Sr - 1u;
+                        p[u] = t0[1u << j];
+                        c[u] = rowk[j];
                     }
                 }
+                double re = 0.0, im = 0.0;
+#pragma unroll
+                for (int u = 0; u < N; u++)
+                    if (u < k) bcfma(re, im, c[u], p[u]);
                 tab[cpos<N>(S)] = make_double2(re, im);
             }
         }
