@@ -147,6 +147,34 @@ static int primes_needed(int n, const int64_t *a, int64_t lda) {
     return r;
 }
 
+// Layers 1..K whose stored values provably lie in [-(2^63 - 1), 2^63 - 1]
+// (returns K, 0 <= K <= n): |F(S)| for |S| = k is at most
+// min(prod_{i<k} R_i, prod_{i<k} (i+1) M_i), R_i = sum_j |a_ij|,
+// M_i = max_j |a_ij| (expand along row k-1: at most R_{k-1}, and at most k
+// times M_{k-1}, times the bound of layer k-1).  Those layers can run in
+// plain 64-bit arithmetic: sums taken mod 2^64 recover a value in that range
+// exactly.
+static int plain_int64_layers(int n, const int64_t *a) {
+    const u128h lim = ((u128h)1 << 63) - 1, top = ~(u128h)0;
+    auto sat_mul = [&](u128h x, u128h y) { return (x != 0 && y > top / x) ? top : x * y; };
+    u128h pr = 1, pf = 1;
+    int K = 0;
+    for (int k = 1; k <= n; k++) {
+        u128h R = 0, M = 0;
+        for (int j = 0; j < n; j++) {
+            const int64_t v = a[(size_t)(k - 1) * n + j];
+            const u128h m = v < 0 ? (u128h)((uint64_t)0 - (uint64_t)v) : (u128h)v;
+            R += m;
+            if (m > M) M = m;
+        }
+        pr = sat_mul(pr, R);
+        pf = sat_mul(pf, (u128h)k * M);
+        if ((pr < pf ? pr : pf) > lim) break;
+        K = k;
+    }
+    return K;
+}
+
 // ------------------------------------------------- Chinese remaindering
 // Mixed-radix (Garner) digits d_i with v = sum d_i prod_{j<i} p_j.
 static void garner_digits(const uint64_t *res, const uint64_t *p, int R, std::vector<uint64_t> &d) {
@@ -504,8 +532,14 @@ static int solve_int(int n, const int64_t *a, int64_t lda, perm_int_t *out, void
     uint64_t *buf0 = (uint64_t *)lay0;
     uint64_t *buf1 = (uint64_t *)(lay0 + align256((size_t)rp * plane * 8));
 
+    // the primes, then a 0 that selects plain 64-bit arithmetic
+    std::vector<uint64_t> up(ps.begin(), ps.begin() + Rt);
+    up.push_back(0);
+    const uint64_t *d_plain = Rt < PERM_MAX_PRIMES ? d_primes + Rt : nullptr;
     HIPCALL(hipMemcpyAsync(d_a, packed.data(), packed.size() * 8, hipMemcpyHostToDevice, s), "upload matrix");
-    HIPCALL(hipMemcpyAsync(d_primes, ps.data(), Rt * 8, hipMemcpyHostToDevice, s), "upload primes");
+    HIPCALL(hipMemcpyAsync(d_primes, up.data(), std::min<size_t>(up.size(), PERM_MAX_PRIMES) * 8,
+                           hipMemcpyHostToDevice, s),
+            "upload primes");
     if (n <= kBatchNMax) {
         // one launch of the on-chip kernel for every prime
         HIPCALL(launch_single_modp(d_a, n, d_primes, Rt, d_res, s), "small-n kernel");
@@ -523,26 +557,46 @@ static int solve_int(int n, const int64_t *a, int64_t lda, perm_int_t *out, void
             const int64_t v = packed[(size_t)i * n + j];
             if (v != 0 && v != 1) binary[i] = 0;
         }
+    // layers 2..K in plain 64-bit arithmetic (one plane), then residues
+    const int K = d_plain ? plain_int64_layers(n, packed.data()) : 0;
+    auto layer = [&](uint64_t *prev, uint64_t *next, int k, const uint64_t *primes, int cnt) -> int {
+        LayerArgs args;
+        const uint32_t grid = plan_layer(n, k, t, chunk, 0, tuned_layer_thin(n), &args);
+        args.binary_row = binary[k - 1];
+        hipEvent_t e0 = nullptr, e1 = nullptr;
+        if (prof) {
+            e0 = profile_event();
+            e1 = profile_event();
+            if (e0) (void)hipEventRecord(e0, s);
+        }
+        HIPCALL(launch_layer_modp(prev, next, plane, d_red, primes, cnt, args, grid, s), "modp layer kernel");
+        if (prof && e0 && e1) {
+            (void)hipEventRecord(e1, s);
+            profile_record(1, e0, e1);
+        }
+        return PERM_OK;
+    };
     for (int s0 = 0; s0 < Rt; s0 += rp) {
         const int cnt = std::min(rp, Rt - s0);
-        HIPCALL(launch_reduce_modp(d_a, n, d_primes + s0, cnt, d_red, buf0, plane, s), "reduce kernel");
         uint64_t *prev = buf0, *next = buf1;
-        for (int k = 2; k <= n; k++) {
-            LayerArgs args;
-            const uint32_t grid = plan_layer(n, k, t, chunk, 0, tuned_layer_thin(n), &args);
-            args.binary_row = binary[k - 1];
-            hipEvent_t e0 = nullptr, e1 = nullptr;
-            if (prof) {
-                e0 = profile_event();
-                e1 = profile_event();
-                if (e0) (void)hipEventRecord(e0, s);
+        int k0 = 2;
+        if (K >= 2) {
+            HIPCALL(launch_reduce_modp(d_a, n, d_plain, 1, d_red, prev, plane, s), "reduce kernel");
+            for (int k = 2; k <= K; k++) {
+                if ((rc = layer(prev, next, k, d_plain, 1)) != PERM_OK) return rc;
+                std::swap(prev, next);
             }
-            HIPCALL(launch_layer_modp(prev, next, plane, d_red, d_primes + s0, cnt, args, grid, s),
-                    "modp layer kernel");
-            if (prof && e0 && e1) {
-                (void)hipEventRecord(e1, s);
-                profile_record(1, e0, e1);
-            }
+            HIPCALL(launch_int64_to_modp(prev, next, plane, binom_host(n, K), d_primes + s0, cnt, s),
+                    "int64 to residues kernel");
+            std::swap(prev, next);
+            // the free buffer takes the reduced first row, which is not used
+            HIPCALL(launch_reduce_modp(d_a, n, d_primes + s0, cnt, d_red, next, plane, s), "reduce kernel");
+            k0 = K + 1;
+        } else {
+            HIPCALL(launch_reduce_modp(d_a, n, d_primes + s0, cnt, d_red, prev, plane, s), "reduce kernel");
+        }
+        for (int k = k0; k <= n; k++) {
+            if ((rc = layer(prev, next, k, d_primes + s0, cnt)) != PERM_OK) return rc;
             std::swap(prev, next);
         }
         HIPCALL(launch_readout_modp(prev, plane, cnt, d_res + s0, s), "readout kernel");

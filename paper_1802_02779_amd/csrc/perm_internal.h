@@ -125,6 +125,8 @@ hipError_t launch_readout_c128(const void *last, void *result, hipStream_t s);
 
 // Integer path: `rp` primes share the sweep; tables are rp planes of `plane`
 // entries each.  `red` holds rp reduced copies of the matrix (rp * n * n).
+// A prime of 0 means plain 64-bit two's-complement arithmetic (entries as
+// they are, outputs truncated to 64 bits), for layers bounded below 2^63.
 hipError_t launch_reduce_modp(const int64_t *a_dev, int n, const uint64_t *primes, int rp,
                               uint64_t *red, uint64_t *layer1, size_t plane, hipStream_t s);
 hipError_t launch_layer_modp(const uint64_t *prev, uint64_t *next, size_t plane,
@@ -132,6 +134,9 @@ hipError_t launch_layer_modp(const uint64_t *prev, uint64_t *next, size_t plane,
                              const LayerArgs &a, uint32_t grid, hipStream_t s);
 hipError_t launch_readout_modp(const uint64_t *last, size_t plane, int rp, uint64_t *out,
                                hipStream_t s);
+// count plain 64-bit values of one layer (src) to rp residue planes (dst).
+hipError_t launch_int64_to_modp(const uint64_t *src, uint64_t *dst, size_t plane, size_t count,
+                                const uint64_t *primes, int rp, hipStream_t s);
 
 // ---- batched on-chip kernel (perm_batch.hip) ----
 struct BatchChunk {

@@ -3,7 +3,10 @@
 // come from perm_layers.hip).
 //
 // Residues mod p = 2^61 - c: the sum of the k products of one stored value is
-// kept exact in 128 bits and folded once per output.
+// kept exact in 128 bits and folded once per output.  The value p = 0 selects
+// plain 64-bit two's-complement arithmetic instead (entries taken as they are,
+// each output truncated to 64 bits): exact for the layers whose stored values
+// and partial sums the host has bounded below 2^63.
 namespace permgpu {
 
 // ------------------------------------------------------------- mod p
@@ -20,6 +23,9 @@ __device__ __forceinline__ uint64_t fold61(u128 x, uint64_t p) {
     return z;
 }
 
+// One output: folded mod p, or (p = 0) the low 64 bits of the exact sum.
+__device__ __forceinline__ uint64_t out_modp(u128 x, uint64_t p) { return p == 0 ? (uint64_t)x : fold61(x, p); }
+
 __global__ void k_reduce_modp(const int64_t *__restrict__ a, int n, const uint64_t *__restrict__ primes,
                               int rp, uint64_t *__restrict__ red, uint64_t *__restrict__ layer1,
                               size_t plane) {
@@ -29,8 +35,11 @@ __global__ void k_reduce_modp(const int64_t *__restrict__ a, int n, const uint64
     for (int r = 0; r < rp; r++) {
         const uint64_t p = primes[r];
         const uint64_t mag = v < 0 ? (uint64_t)0 - (uint64_t)v : (uint64_t)v;
-        uint64_t m = mag % p;
-        if (v < 0 && m != 0) m = p - m;
+        uint64_t m = (uint64_t)v;
+        if (p != 0) {
+            m = mag % p;
+            if (v < 0 && m != 0) m = p - m;
+        }
         red[(size_t)r * n * n + i] = m;
         if (i < n) layer1[(size_t)r * plane + i] = m;
     }
@@ -120,7 +129,7 @@ __device__ void layer_modp_thin(const uint64_t *__restrict__ prev, uint64_t *__r
         q++;
     }
 #pragma unroll
-    for (int r = 0; r < RP; r++) next[(size_t)r * plane + base_out + rr] = fold61(acc[r], primes[r]);
+    for (int r = 0; r < RP; r++) next[(size_t)r * plane + base_out + rr] = out_modp(acc[r], primes[r]);
 }
 
 // BIN: every entry of this layer's row of A is 0 or 1 (then equal in every
@@ -248,7 +257,7 @@ __global__ __launch_bounds__(kLayerBlock) void k_layer_modp(const uint64_t *__re
             }
         }
 #pragma unroll
-        for (int r = 0; r < RP; r++) next[(size_t)r * plane + ti.base_out + rr] = fold61(acc[r], pr[r]);
+        for (int r = 0; r < RP; r++) next[(size_t)r * plane + ti.base_out + rr] = out_modp(acc[r], pr[r]);
     }
 }
 
@@ -279,6 +288,30 @@ hipError_t launch_layer_modp(const uint64_t *prev, uint64_t *next, size_t plane,
     const size_t lds = layer_lds_bytes_modp(a, rp);
     if (a.binary_row) launch_modp_t<true>(prev, next, plane, red, primes, rp, a, grid, lds, s);
     else launch_modp_t<false>(prev, next, plane, red, primes, rp, a, grid, lds, s);
+    return hipGetLastError();
+}
+
+// A layer of plain 64-bit values (two's complement) to residues mod rp primes:
+// dst plane r, entry i = src[i] mod primes[r] in [0, p).
+__global__ void k_int64_to_modp(const uint64_t *__restrict__ src, uint64_t *__restrict__ dst, size_t plane,
+                                size_t count, const uint64_t *__restrict__ primes, int rp) {
+    const size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= count) return;
+    const int64_t v = (int64_t)src[i];
+    const uint64_t mag = v < 0 ? (uint64_t)0 - (uint64_t)v : (uint64_t)v;
+    for (int r = 0; r < rp; r++) {
+        const uint64_t p = primes[r];
+        uint64_t m = fold61((u128)mag, p);
+        if (v < 0 && m != 0) m = p - m;
+        dst[(size_t)r * plane + i] = m;
+    }
+}
+
+hipError_t launch_int64_to_modp(const uint64_t *src, uint64_t *dst, size_t plane, size_t count,
+                                const uint64_t *primes, int rp, hipStream_t s) {
+    if (count == 0) return hipSuccess;
+    hipLaunchKernelGGL(k_int64_to_modp, dim3((unsigned)((count + 255) / 256)), dim3(256), 0, s, src, dst, plane,
+                       count, primes, rp);
     return hipGetLastError();
 }
 

@@ -253,3 +253,19 @@ def test_int_invariances_and_small_workspace(P):
     from math import comb
     one = P.perm_workspace_bytes(P.PERM_INT64, n) - 2 * 2 * 8 * max(comb(n, k) for k in range(n + 1)) + 1024
     assert P.perm_solve(A, workspace=P.device_buffer(one)) == ref
+
+
+@pytest.mark.parametrize("n,c", [(16, 1), (20, 1), (22, 1), (24, 3), (24, 7), (21, 2)])
+def test_int_plain_prefix_switch(P, n, c):
+    """c * J with row signs: every stored value of layer k is +-k! c^k, equal
+    to the bound that decides how many layers run in plain 64-bit arithmetic
+    before the residues take over (all layers for 1 * J_16 and 1 * J_20, up to
+    k = 20 for 1 * J_22, k = 14 for 3 * J, k = 12 for 7 * J, k = 16 for 2 * J), so a layer
+    taken past the bound would overflow and show."""
+    sign = np.where(np.arange(n) % 3 == 1, -1, 1).astype(np.int64)
+    A = c * np.ones((n, n), dtype=np.int64) * sign[:, None]
+    want = math.factorial(n) * c ** n * int(np.prod(sign))
+    print(f"[gpu] int plain prefix n={n} c={c}", flush=True)
+    assert P.perm_solve(A) == want
+    B = inputs.uniform_int(n, -c, c, seed=n + c)
+    assert P.perm_solve(B) == native.per_int(B)
