@@ -320,7 +320,9 @@ int perm_server_destroy(perm_server_t *s);
  *                      0 = library default.
  *   layer_xcd_remap[n] tiles dealt to each of the 8 XCDs in runs of this many
  *                      consecutive tiles; 0 = hardware order, -1 = default.
- *   layer_flags[n]     bit 0: non-temporal stores of layer outputs.
+ *   layer_flags[n]     bit 0: non-temporal stores of layer outputs;
+ *                      bit 1: the exact integer sweep's plain 64-bit layers
+ *                      (those bounded below 2^63) use layer_t + 1 low columns.
  *   layer_thin[n]      tiles with fewer outputs than this are computed one
  *                      output per thread instead of staging a window in LDS;
  *                      0 = library default (128), -1 = never.

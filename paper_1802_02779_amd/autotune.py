@@ -1,6 +1,6 @@
 """Autotuner for libpermgpu's tile and schedule parameters.
 
-    python -m paper_1802_02779_amd.autotune [--out FILE] [--layer-n 20,24,26,28,30] [--batch]
+    python -m paper_1802_02779_amd.autotune [--out FILE] [--layer-n 20,24,26,28,30] [--int-n 26,28,30] [--batch]
 
 For each order n it times the candidates of one path on seeded synthetic
 inputs through the C ABI and keeps the fastest candidate whose result is
@@ -10,6 +10,9 @@ disqualifies the candidate):
 
 * layer sweep (perm_solve_async, complex128): low-window width t, XCD chunk
   of the tile order, non-temporal output stores, per-thread threshold;
+* exact integer sweep (perm_solve, int64 Bernoulli input): whether its plain
+  64-bit layers take one low column more than the complex sweep (bit 1 of
+  layer_flags; the values must come out identical);
 * batched kernel (perm_solve_batch, complex128): threads per matrix.
 
 The winners go into the process-wide tuning table (perm_tuning_set) and are
@@ -94,6 +97,33 @@ def tune_layer(perm, inputs, torch, n: int, log=_log, reps: int = 3):
     return best
 
 
+def tune_int_plain(perm, inputs, torch, n: int, log=_log, reps: int = 5):
+    """Bit 1 of layer_flags[n]: whether the exact integer sweep's plain 64-bit
+    layers take one low column more than layer_t.  Timed on a Bernoulli 0/1
+    matrix (most layers plain); kept only if the value is unchanged."""
+    B = inputs.bernoulli01(n, seed=n)
+    ws = perm.device_buffer(perm.perm_workspace_bytes(perm.PERM_INT64, n))
+    base = perm.perm_tuning_get()
+    res = {}
+    for bit in (0, 2):
+        cand = perm.perm_tuning_t.from_buffer_copy(base)
+        cand.layer_flags[n] = (cand.layer_flags[n] & ~2) | bit
+        perm.perm_tuning_set(cand)
+        out = []
+        ms = _time_ms(lambda: out.append(perm.perm_solve(B, workspace=ws)), reps, torch.cuda.synchronize)  # noqa: B023
+        res[bit] = (ms, out[-1])
+    if res[0][1] != res[2][1]:
+        raise RuntimeError(f"integer n={n}: values differ between the two widths")
+    bit = 2 if res[2][0] < res[0][0] else 0
+    final = perm.perm_tuning_t.from_buffer_copy(base)
+    final.layer_flags[n] = (final.layer_flags[n] & ~2) | bit
+    perm.perm_tuning_set(final)
+    log(f"int n={n}: plain layers at layer_t {res[0][0]:.3f} ms, at layer_t + 1 {res[2][0]:.3f} ms "
+        f"-> bit {bit >> 1}")
+    del ws
+    return bit
+
+
 def tune_batch(perm, inputs, torch, n: int, count: int = 1 << 16, log=_log, reps: int = 7):
     C = perm.PERM_COMPLEX128
     U = inputs.haar_unitary(64, seed=2018)
@@ -137,6 +167,8 @@ def main(argv=None):
     ap = argparse.ArgumentParser()
     ap.add_argument("--out", default=DEFAULT_FILE)
     ap.add_argument("--layer-n", default="16,20,24,26,28,30")
+    ap.add_argument("--int-n", default="",
+                    help="orders whose integer plain-layer width is tuned (layer_flags bit 1)")
     ap.add_argument("--batch", action="store_true")
     args = ap.parse_args(argv)
     sys.path.insert(0, os.path.dirname(HERE))
@@ -149,6 +181,9 @@ def main(argv=None):
         perm.perm_tuning_load(args.out)
     for n in [int(x) for x in args.layer_n.split(",") if x]:
         tune_layer(perm, inputs, torch, n)
+        torch.cuda.empty_cache()
+    for n in [int(x) for x in args.int_n.split(",") if x]:
+        tune_int_plain(perm, inputs, torch, n)
         torch.cuda.empty_cache()
     if args.batch:
         for n in range(3, 13):

@@ -344,6 +344,14 @@ int tuned_layer_flags(int n) {
     return g_tune.layer_flags[n];
 }
 
+// Low columns of the integer sweep's plain 64-bit layers: layer_t, or one
+// more with bit 1 of layer_flags (8-byte values fill a window of t + 1
+// columns with about the bytes of a complex window of t).
+static int tuned_plain_layer_t(int n) {
+    const int t = tuned_layer_t(n);
+    return (tuned_layer_flags(n) & 2) ? valid_layer_t(n, t + 1) : t;
+}
+
 // Threads per matrix in the batched kernel: a power of two in [16, block]
 // with block/G matrices fitting the workgroup's LDS and, for the complex
 // kernel, its register staging of one matrix entry per thread (the integer
@@ -559,9 +567,10 @@ static int solve_int(int n, const int64_t *a, int64_t lda, perm_int_t *out, void
         }
     // layers 2..K in plain 64-bit arithmetic (one plane), then residues
     const int K = d_plain ? plain_int64_layers(n, packed.data()) : 0;
-    auto layer = [&](uint64_t *prev, uint64_t *next, int k, const uint64_t *primes, int cnt) -> int {
+    const int t_plain = tuned_plain_layer_t(n);
+    auto layer = [&](uint64_t *prev, uint64_t *next, int k, const uint64_t *primes, int cnt, int tk) -> int {
         LayerArgs args;
-        const uint32_t grid = plan_layer(n, k, t, chunk, 0, tuned_layer_thin(n), &args);
+        const uint32_t grid = plan_layer(n, k, tk, chunk, 0, tuned_layer_thin(n), &args);
         args.binary_row = binary[k - 1];
         hipEvent_t e0 = nullptr, e1 = nullptr;
         if (prof) {
@@ -583,7 +592,7 @@ static int solve_int(int n, const int64_t *a, int64_t lda, perm_int_t *out, void
         if (K >= 2) {
             HIPCALL(launch_reduce_modp(d_a, n, d_plain, 1, d_red, prev, plane, s), "reduce kernel");
             for (int k = 2; k <= K; k++) {
-                if ((rc = layer(prev, next, k, d_plain, 1)) != PERM_OK) return rc;
+                if ((rc = layer(prev, next, k, d_plain, 1, t_plain)) != PERM_OK) return rc;
                 std::swap(prev, next);
             }
             HIPCALL(launch_int64_to_modp(prev, next, plane, binom_host(n, K), d_primes + s0, cnt, s),
@@ -596,7 +605,7 @@ static int solve_int(int n, const int64_t *a, int64_t lda, perm_int_t *out, void
             HIPCALL(launch_reduce_modp(d_a, n, d_primes + s0, cnt, d_red, prev, plane, s), "reduce kernel");
         }
         for (int k = k0; k <= n; k++) {
-            if ((rc = layer(prev, next, k, d_primes + s0, cnt)) != PERM_OK) return rc;
+            if ((rc = layer(prev, next, k, d_primes + s0, cnt, t)) != PERM_OK) return rc;
             std::swap(prev, next);
         }
         HIPCALL(launch_readout_modp(prev, plane, cnt, d_res + s0, s), "readout kernel");
@@ -1240,7 +1249,7 @@ int perm_tuning_set(const perm_tuning_t *in) {
             return set_error(PERM_EINVAL, "layer_t[%d] = %d impossible", n, t);
         if (in->layer_xcd_remap[n] < -1 || in->layer_xcd_remap[n] > 4096)
             return set_error(PERM_EINVAL, "layer_xcd_remap[%d] = %d", n, in->layer_xcd_remap[n]);
-        if (in->layer_flags[n] & ~1)
+        if (in->layer_flags[n] & ~3)
             return set_error(PERM_EINVAL, "layer_flags[%d] = %d", n, in->layer_flags[n]);
         if (in->layer_thin[n] < -1 || in->layer_thin[n] > 65536)
             return set_error(PERM_EINVAL, "layer_thin[%d] = %d", n, in->layer_thin[n]);

@@ -269,3 +269,23 @@ def test_int_plain_prefix_switch(P, n, c):
     assert P.perm_solve(A) == want
     B = inputs.uniform_int(n, -c, c, seed=n + c)
     assert P.perm_solve(B) == native.per_int(B)
+
+
+@pytest.mark.parametrize("n", [20, 24])
+def test_int_plain_layer_width_variants(P, n):
+    """Bit 1 of layer_flags widens the low window of the plain 64-bit layers
+    only: every width gives the same exact value."""
+    A01 = inputs.bernoulli01(n, seed=3)
+    A9 = inputs.uniform_int(n, 0, 9, seed=3)
+    want = (native.per_int(A01), native.per_int(A9))
+    saved = P.perm_tuning_get()
+    try:
+        for t in range(max(1, n - 22), 15):
+            for flags in (0, 2, 3):
+                tu = P.perm_tuning_t.from_buffer_copy(saved)
+                tu.layer_t[n] = t
+                tu.layer_flags[n] = flags
+                P.perm_tuning_set(tu)
+                assert (P.perm_solve(A01), P.perm_solve(A9)) == want, (n, t, flags)
+    finally:
+        P.perm_tuning_set(saved)
