@@ -620,6 +620,32 @@ int primes_needed_multi(const MultiPlan &P, const int64_t *a, int64_t lda) {
     return have > need ? r : PERM_MAX_PRIMES + 1;
 }
 
+// Layers 1..K whose stored values lie in [-(2^63 - 1), 2^63 - 1]: G(c) has
+// one term per distinct column of c, so with R_i = sum_j |a_ij| and
+// M_i = max_j |a_ij| over the m columns, |G(c)| for |c| = k is at most
+// min(R_{k-1}, min(k, m) M_{k-1}) times the bound of layer k - 1.  Those
+// layers run in plain 64-bit arithmetic (sums mod 2^64 recover a value in
+// that range exactly).
+int plain_int64_layers_multi(const MultiPlan &P, const int64_t *a, int64_t lda) {
+    const u128m lim = ((u128m)1 << 63) - 1;
+    u128m B = 1;
+    int K = 0;
+    for (int k = 1; k <= P.n; k++) {
+        u128m R = 0, M = 0;
+        for (int j = 0; j < P.m; j++) {
+            const int64_t v = a[(int64_t)(k - 1) * lda + j];
+            const u128m x = v < 0 ? (u128m)((uint64_t)0 - (uint64_t)v) : (u128m)v;
+            R += x;
+            if (x > M) M = x;
+        }
+        const u128m f = std::min(R, (u128m)std::min(k, P.m) * M);
+        if (f != 0 && B > lim / f) break;
+        B *= f;
+        K = k;
+    }
+    return K;
+}
+
 struct LayoutI {
     size_t primes, res, red, bufs;
 };
@@ -646,7 +672,12 @@ int multi_int(const MultiPlan &P, const int64_t *a, int64_t lda, perm_int_t *out
     if (Rt > PERM_MAX_PRIMES) return set_error(PERM_ERANGE, "needs more than %d primes", PERM_MAX_PRIMES - 1);
     const auto &ps = primes61();
     const size_t nm = (size_t)P.n * P.m;
-    std::vector<uint64_t> red(Rt * nm);
+    // layers 2..K in plain 64-bit arithmetic ("prime" 0, entries as they are,
+    // block Rt of red), then residues
+    const int K = Rt < PERM_MAX_PRIMES ? plain_int64_layers_multi(P, a, lda) : 0;
+    std::vector<uint64_t> red((Rt + 1) * nm);
+    for (int i = 0; i < P.n; i++)
+        for (int j = 0; j < P.m; j++) red[Rt * nm + (size_t)i * P.m + j] = (uint64_t)a[(int64_t)i * lda + j];
     for (int r = 0; r < Rt; r++)
         for (int i = 0; i < P.n; i++)
             for (int j = 0; j < P.m; j++) {
@@ -663,31 +694,55 @@ int multi_int(const MultiPlan &P, const int64_t *a, int64_t lda, perm_int_t *out
     const size_t plane = P.max_layer;
     uint64_t *buf0 = (uint64_t *)(base + Ly.bufs);
     uint64_t *buf1 = (uint64_t *)(base + Ly.bufs + a256((size_t)rp * plane * 8));
-    MHIP(hipMemcpyAsync(d_primes, ps.data(), Rt * 8, hipMemcpyHostToDevice, s), "upload primes");
-    MHIP(hipMemcpyAsync(d_red, red.data(), red.size() * 8, hipMemcpyHostToDevice, s), "upload residues");
+    std::vector<uint64_t> up(ps.begin(), ps.begin() + Rt);
+    up.push_back(0);
+    const size_t nup = K >= 2 ? up.size() : (size_t)Rt;
+    MHIP(hipMemcpyAsync(d_primes, up.data(), nup * 8, hipMemcpyHostToDevice, s), "upload primes");
+    MHIP(hipMemcpyAsync(d_red, red.data(), (K >= 2 ? red.size() : Rt * nm) * 8, hipMemcpyHostToDevice, s),
+         "upload residues");
     const char *d_plan = nullptr;
     const int rc = device_plan(P, &d_plan);
     if (rc) return rc;
     const bool prof = profiling_on();
+    auto layer = [&](const uint64_t *prev, uint64_t *next, int k, const uint64_t *gred, const uint64_t *primes,
+                     int cnt) -> int {
+        const MultiLayerArgs g = layer_args(P, d_plan, k);
+        hipEvent_t e0 = nullptr, e1 = nullptr;
+        if (prof) {
+            e0 = profile_event();
+            e1 = profile_event();
+            if (e0) (void)hipEventRecord(e0, s);
+        }
+        MHIP(launch_multi_layer_modp(prev, next, plane, gred, primes, cnt, g, s), "repeated-column modp layer kernel");
+        if (prof && e0 && e1) {
+            (void)hipEventRecord(e1, s);
+            profile_record(5, e0, e1);
+        }
+        return PERM_OK;
+    };
     for (int s0 = 0; s0 < Rt; s0 += rp) {
         const int cnt = std::min(rp, Rt - s0);
         const uint64_t *gred = d_red + (size_t)s0 * nm;
-        MHIP(launch_multi_init_modp(gred, P.n, P.m, cnt, buf0, plane, s), "init kernel");
         uint64_t *prev = buf0, *next = buf1;
-        for (int k = 2; k <= P.n; k++) {
-            const MultiLayerArgs g = layer_args(P, d_plan, k);
-            hipEvent_t e0 = nullptr, e1 = nullptr;
-            if (prof) {
-                e0 = profile_event();
-                e1 = profile_event();
-                if (e0) (void)hipEventRecord(e0, s);
+        int k0 = 2;
+        if (K >= 2) {
+            const uint64_t *pred = d_red + (size_t)Rt * nm, *pzero = d_primes + Rt;
+            MHIP(launch_multi_init_modp(pred, P.n, P.m, 1, prev, plane, s), "init kernel");
+            for (int k = 2; k <= K; k++) {
+                const int lrc = layer(prev, next, k, pred, pzero, 1);
+                if (lrc) return lrc;
+                std::swap(prev, next);
             }
-            MHIP(launch_multi_layer_modp(prev, next, plane, gred, d_primes + s0, cnt, g, s),
-                 "repeated-column modp layer kernel");
-            if (prof && e0 && e1) {
-                (void)hipEventRecord(e1, s);
-                profile_record(5, e0, e1);
-            }
+            MHIP(launch_int64_to_modp(prev, next, plane, P.size[K], d_primes + s0, cnt, s),
+                 "int64 to residues kernel");
+            std::swap(prev, next);
+            k0 = K + 1;
+        } else {
+            MHIP(launch_multi_init_modp(gred, P.n, P.m, cnt, prev, plane, s), "init kernel");
+        }
+        for (int k = k0; k <= P.n; k++) {
+            const int lrc = layer(prev, next, k, gred, d_primes + s0, cnt);
+            if (lrc) return lrc;
             std::swap(prev, next);
         }
         MHIP(launch_readout_modp(prev, plane, cnt, d_res + s0, s), "readout kernel");

@@ -50,9 +50,13 @@ hipError_t launch_multi_pack_c128(const void *a_dev, int64_t lda, int n, int m, 
 hipError_t launch_multi_layer_c128(const void *prev, void *next, const void *row, const MultiLayerArgs &g,
                                    uint32_t max_window, hipStream_t s);
 hipError_t launch_multi_readout_c128(const void *last, double scale, void *out, hipStream_t s);
-// red: residues [prime][n][m]; layer1 planes get row 0.
+// red: residues [prime][n][m]; layer1 planes get row 0.  A prime of 0 means
+// plain 64-bit arithmetic (red holds the entries themselves).
 hipError_t launch_multi_init_modp(const uint64_t *red, int n, int m, int rp, uint64_t *layer1, size_t plane,
                                   hipStream_t s);
+// A layer of plain 64-bit values to rp residue planes (perm_layer_modp.hip).
+hipError_t launch_int64_to_modp(const uint64_t *src, uint64_t *dst, size_t plane, size_t count,
+                                const uint64_t *primes, int rp, hipStream_t s);
 hipError_t launch_multi_layer_modp(const uint64_t *prev, uint64_t *next, size_t plane, const uint64_t *red,
                                    const uint64_t *primes, int rp, const MultiLayerArgs &g, hipStream_t s);
 

@@ -226,8 +226,9 @@ hipError_t launch_multi_init_modp(const uint64_t *red, int n, int m, int rp, uin
 }
 
 // Residues of a[k-1][*] for RP primes; each output sums at most m <= 64
-// products below 2^122 exactly in 128 bits, then one fold.  Predecessors
-// are read from HBM / cache directly (RP planes rarely fit one LDS window).
+// products below 2^122 exactly in 128 bits, then one fold (the prime 0:
+// plain 64-bit arithmetic, see out_modp).  Predecessors are read from HBM /
+// cache directly (RP planes rarely fit one LDS window).
 template <int RP>
 __device__ __forceinline__ void multi_output_modp(const uint64_t *__restrict__ prev, uint64_t *__restrict__ next,
                                                   size_t plane, const uint64_t (*s_row)[kMultiMMax],
@@ -251,7 +252,7 @@ __device__ __forceinline__ void multi_output_modp(const uint64_t *__restrict__ p
         for (int r = 0; r < RP; r++) acc[r] += (u128)s_row[r][col] * prev[(size_t)r * plane + b + rr];
     }
 #pragma unroll
-    for (int r = 0; r < RP; r++) next[(size_t)r * plane + t.base_out + rr] = fold61(acc[r], primes[r]);
+    for (int r = 0; r < RP; r++) next[(size_t)r * plane + t.base_out + rr] = out_modp(acc[r], primes[r]);
 }
 
 // The same split into thin tiles (one per wave) and workgroup tiles as the

@@ -203,3 +203,19 @@ def test_bunched_rows_and_columns(P, rm, cm):
     else:
         ref = native.per_multi_c128(np.repeat(Z, rm, axis=0), cm)
     assert bits(got) == bits(ref)
+
+
+@pytest.mark.parametrize("c,t", [(3, [2] * 12), (1, [3] * 8 + [1] * 4), (2, [1] * 6 + [4] * 4)])
+def test_int_plain_prefix_switch(P, c, t):
+    """c * (an n x m block of ones) with row signs: count vectors whose used
+    columns appear once reach the bound that decides how many layers run in
+    plain 64-bit arithmetic before the residues take over; the value is
+    n! c^n times the signs, and a random block matches the oracle."""
+    n, m = sum(t), len(t)
+    sign = np.where(np.arange(n) % 4 == 2, -1, 1).astype(np.int64)
+    A = c * np.ones((n, m), dtype=np.int64) * sign[:, None]
+    print(f"[gpu] multi int plain prefix c={c} mult={t}", flush=True)
+    assert P.perm_solve_multi(A, t) == math.factorial(n) * c ** n * int(np.prod(sign))
+    rng = np.random.default_rng(n * 7 + c)
+    B = rng.integers(-c, c + 1, size=(n, m), dtype=np.int64)
+    assert P.perm_solve_multi(B, t) == native.per_multi_int(B, t)
