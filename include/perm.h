@@ -22,7 +22,10 @@
  *   PERM_INT64 -- exact: per(A) mod several primes p < 2^61 (largest first),
  *     chosen so their product exceeds twice a bound on |per(A)|, plus one
  *     redundant prime that must agree; recombined by Chinese remaindering on
- *     the host into a signed multi-limb integer (perm_int_t).
+ *     the host into a signed multi-limb integer (perm_int_t).  The layers
+ *     whose stored values are bounded below 2^63 (by the row sums and by
+ *     k! times the row maxima of |A|) are computed exactly in 64-bit
+ *     integers and reduced mod the primes once, after the last of them.
  *
  * Conventions shared by every call:
  *   - Return value: PERM_OK (0), PERM_PENDING (1, server only) or a negative
@@ -183,7 +186,8 @@ int perm_ryser_async(int n, const perm_c128_t *a_dev, int64_t lda, perm_c128_t *
  * in that order); with every mult[j] = 1 the result is bitwise perm_solve's
  * (that case runs the subset path).  int64 is exact: G mod the 61-bit primes
  * (bound of the expanded matrix, one redundant prime), recombined on the
- * host, times prod_j mult[j]!.
+ * host, times prod_j mult[j]!; as for perm_solve, the layers whose values are
+ * bounded below 2^63 run in exact 64-bit integers first.
  *
  * Arguments: n >= 0 rows (= sum of mult), m distinct columns (0 <= m <= n;
  * m = 0 only with n = 0), mult host int32_t[m], every entry >= 1; a row-major
