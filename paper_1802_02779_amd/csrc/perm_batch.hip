@@ -100,25 +100,40 @@ constexpr int cbinom(int n, int k) {
     return r;
 }
 
+// F({x, y}) for x < y: the stored value of layer 2, formed from the matrix
+// (row 0 entries are the stored values of layer 1) with its chain, j = x then
+// j = y.
+__device__ __forceinline__ double2 pair_value(const double2 *mat, int N, uint32_t x, uint32_t y) {
+    double re = 0.0, im = 0.0;
+    bcfma(re, im, mat[N + x], mat[y]);
+    bcfma(re, im, mat[N + y], mat[x]);
+    return make_double2(re, im);
+}
+
 // One chunk of matrices of order N.  Layer by layer, each lane computes whole
 // stored values F(S) with the fixed chain over the columns of S in ascending
-// order (k is a compile-time constant in each unrolled layer).
+// order (k is a compile-time constant in each unrolled layer).  Layers 1 and
+// 2 are not stored: layer 3 forms its predecessors from the matrix with the
+// same chains (pair_value).  Layer N - 1 has N values, all in the first N
+// lanes of one wave, so the last value is formed after a wave-level fence
+// instead of a workgroup barrier.
 // mi is the result index of this thread's matrix (read with the prefetch).
 template <int N>
 __device__ __forceinline__ void batch_chunk_c128(const BatchChunk ch, int nmax, const uint16_t *s_masks, double2 *area,
                                                  uint32_t mi, double2 *__restrict__ results) {
+    static_assert(N >= 3, "orders below 3 take batch_chunk_tiny_c128");
     const int lg = ch.group, G = 1 << lg;
     const int gi = threadIdx.x >> lg, lane = threadIdx.x & (G - 1);
     constexpr int PER = (1 << N) + N * N;
     double2 *tab = area + (size_t)gi * PER;
-    double2 *mat = tab + (1 << N);
+    const double2 *mat = tab + (1 << N);
     const bool active = gi < (int)ch.count;
-    if (active)
-        for (int j = lane; j < N; j += G) tab[cpos<N>(1u << j)] = mat[j];
-    __syncthreads();
 #pragma unroll
-    for (int k = 2; k <= N; k++) {
-        if (active) {
+    for (int k = 3; k <= N; k++) {
+        // the last layer (one value) in lane 0 of the wave that holds layer N - 1
+        const bool last = k == N;
+        if (last && N > 3) __builtin_amdgcn_fence(__ATOMIC_ACQ_REL, "wavefront");
+        if (active && (!last || lane == 0)) {
             const uint16_t *ml = s_masks + mask_block(kBatchNMax, k);
             // row k-1 of A, read per term at the lane's own column
             const double2 *rowk = mat + (k - 1) * N;
@@ -139,7 +154,13 @@ __device__ __forceinline__ void batch_chunk_c128(const BatchChunk ch, int nmax, 
                     if (u < k) {
                         const uint32_t j = (uint32_t)__builtin_ctz(Sr);
                         Sr &= Sr - 1u;
-                        p[u] = t0[1u << j];
+                        if (k == 3) {
+                            const uint32_t rest = S ^ (1u << j);
+                            const uint32_t x = (uint32_t)__builtin_ctz(rest);
+                            p[u] = pair_value(mat, N, x, (uint32_t)__builtin_ctz(rest ^ (1u << x)));
+                        } else {
+                            p[u] = t0[1u << j];
+                        }
                         c[u] = rowk[j];
                     }
                 }
@@ -147,12 +168,12 @@ __device__ __forceinline__ void batch_chunk_c128(const BatchChunk ch, int nmax, 
 #pragma unroll
                 for (int u = 0; u < N; u++)
                     if (u < k) bcfma(re, im, c[u], p[u]);
-                tab[cpos<N>(S)] = make_double2(re, im);
+                if (last) results[mi] = make_double2(re, im);
+                else tab[cpos<N>(S)] = make_double2(re, im);
             }
         }
-        __syncthreads();
+        if (k < N - 1) __syncthreads();
     }
-    if (active && lane == 0) results[mi] = tab[cpos<N>((1u << N) - 1)];
     __syncthreads();
 }
 
