@@ -116,7 +116,8 @@ __device__ __forceinline__ double2 pair_value(const double2 *mat, int N, uint32_
 // 2 are not stored: layer 3 forms its predecessors from the matrix with the
 // same chains (pair_value).  Layer N - 1 has N values, all in the first N
 // lanes of one wave, so the last value is formed after a wave-level fence
-// instead of a workgroup barrier.
+// instead of a workgroup barrier; groups of at most 64 lanes (one wave) use
+// such fences between all their layers.
 // mi is the result index of this thread's matrix (read with the prefetch).
 template <int N>
 __device__ __forceinline__ void batch_chunk_c128(const BatchChunk ch, int nmax, const uint16_t *s_masks, double2 *area,
@@ -172,7 +173,12 @@ __device__ __forceinline__ void batch_chunk_c128(const BatchChunk ch, int nmax, 
                 else tab[cpos<N>(S)] = make_double2(re, im);
             }
         }
-        if (k < N - 1) __syncthreads();
+        if (k < N - 1) {
+            // a group of at most 64 lanes lies in one wave: its layers need
+            // only that wave's LDS traffic ordered (the branch is uniform)
+            if (G <= 64) __builtin_amdgcn_fence(__ATOMIC_ACQ_REL, "wavefront");
+            else __syncthreads();
+        }
     }
     __syncthreads();
 }
