@@ -121,3 +121,31 @@ def test_batch_int64(P):
         A = mats[offsets[i]:offsets[i] + n * n].reshape(n, n)
         ref = exact.per_definition(A) if n <= 6 else native.per_int(A)
         assert got[i] == ref, (i, n)
+
+
+def test_batch_full_size_sampled(P):
+    """The timed workload at full size (2^20 submatrices of order 3..12 of the
+    seeded 64x64 Haar unitary, one graph launch, then a replay): 1500 sampled
+    outputs, plus the first and last of every order, bitwise equal to the
+    oracle's; the replay bitwise equal to the first launch."""
+    import torch
+    count = 1 << 20
+    U = inputs.haar_unitary(64, seed=2018)
+    b = inputs.submatrix_batch(U, count, 3, 12, seed=1)
+    print("[gpu] batch 2^20 full size", flush=True)
+    got, d_mats, results, ws = run_batch(P, b, flags=P.PERM_BATCH_GRAPH)
+    rng = np.random.default_rng(7)
+    idx = set(rng.choice(count, size=1500, replace=False).tolist())
+    for n in range(3, 13):
+        where = np.flatnonzero(b.ns == n)
+        idx.update([int(where[0]), int(where[-1])])
+    idx = sorted(idx)
+    ref = c_bits_arr([native.per_c128(b.matrix(i), mode=native.MODE_MEMO) for i in idx])
+    assert (c_bits_arr(got[idx]) == ref).all()
+    results.zero_()
+    torch.cuda.synchronize()
+    P.perm_solve_batch(P.PERM_COMPLEX128, b.ns, b.offsets, d_mats, results, ws,
+                       flags=P.PERM_BATCH_GRAPH | P.PERM_BATCH_REUSE | P.PERM_BATCH_SYNC)
+    assert (c_bits_arr(results.cpu().numpy()) == c_bits_arr(got)).all()
+    del d_mats, results, ws
+    torch.cuda.empty_cache()
