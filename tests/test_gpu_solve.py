@@ -289,3 +289,34 @@ def test_int_plain_layer_width_variants(P, n):
                 assert (P.perm_solve(A01), P.perm_solve(A9)) == want, (n, t, flags)
     finally:
         P.perm_tuning_set(saved)
+
+
+def test_full_sizes_under_shipped_tuning(P, golden):
+    """The timed workloads in the configuration bench.py times: the shipped
+    tuning table loaded, device-resident complex solves (n = 26, 28) and the
+    n = 30 0/1 exact solve, against the stored oracle values."""
+    import os
+    import torch
+    path = os.path.join(os.path.dirname(os.path.dirname(os.path.abspath(__file__))),
+                        "paper_1802_02779_amd", "tuning", "gfx950.json")
+    saved = P.perm_tuning_get()
+    try:
+        if P.perm_tuning_load(path) != 0:
+            pytest.skip("the shipped tuning table is for another GPU key")
+        for key, n in (("c128_n26_s0", 26), ("c128_n28_s0", 28)):
+            g = golden[key]
+            A = inputs.complex_gaussian(n, seed=0)
+            d_a = torch.from_numpy(A).cuda()
+            d_r = torch.zeros(1, dtype=torch.complex128, device="cuda")
+            ws = P.device_buffer(P.perm_workspace_bytes(P.PERM_COMPLEX128, n))
+            print(f"[gpu] shipped tuning {key}", flush=True)
+            for _ in range(2):
+                P.perm_solve_async(n, d_a, n, d_r, ws)
+            z = complex(d_r.cpu().numpy()[0])
+            assert c_bits(z) == (int(g["re_bits"], 16), int(g["im_bits"], 16)), key
+            del ws
+        print("[gpu] shipped tuning int n=30", flush=True)
+        assert P.perm_solve(inputs.bernoulli01(30, seed=0)) == int(golden["int_n30_bern_s0"]["value"])
+    finally:
+        P.perm_tuning_set(saved)
+        torch.cuda.empty_cache()
