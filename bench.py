@@ -731,7 +731,14 @@ def cpu_baseline(inputs, log):
     native.per_c128(A22, mode=native.MODE_MEMO)
     memo22 = time.perf_counter() - t0
     log(f"oracle one core: n=24 layers {one24:.2f} s, n=22 memo {memo22:.2f} s")
+    # context only: the paper's section 5.2 operation-rate model for n = 28,
+    # with the Store-zechin counts M(n) = n(2^(n-1) - 1), A(n) = (n-2) 2^(n-1) + 1
+    from oracle import exact
+    m28, a28 = 28 * (2 ** 27 - 1), 26 * 2 ** 27 + 1
+    paper = {mach: round(exact.machine_time_ms(m28, a28, mach) / 86400e3, 1) for mach in ("ENIAC", "TRADIC")}
+    log(f"paper's rate model, n=28 Store-zechin: ENIAC {paper['ENIAC']} days, TRADIC {paper['TRADIC']} days")
     return {"value": round(1.0 / dt, 5), "unit": "perms/s", "cores": cores, "kind": "oracle",
+            "paper_rate_model_n28_days": paper,
             "sample": "one full 28x28 complex128 permanent (all 2^28 stored sub-permanents), "
                       f"{dt:.1f} s wall",
             "int_n10_us_median": round(int10_us, 1),
