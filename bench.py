@@ -46,16 +46,15 @@ def layer_bytes(n: int, elem: int = 16) -> int:
 
 def plain_layers(A) -> int:
     """Layers 1..K whose stored values the integer path bounds below 2^63
-    (min of prod_{i<k} sum_j |a_ij| and prod_{i<k} (i+1) max_j |a_ij|); those
-    run in plain 64-bit arithmetic, the rest in residues."""
+    (the product over rows i < k of min(sum_j |a_ij|, (i+1) max_j |a_ij|));
+    those run in plain 64-bit arithmetic, the rest in residues."""
     n = A.shape[0]
-    pr = pf = 1
+    B = 1
     K = 0
     for k in range(1, n + 1):
         row = [abs(int(x)) for x in A[k - 1]]
-        pr *= sum(row)
-        pf *= k * max(row)
-        if min(pr, pf) > 2 ** 63 - 1:
+        B *= min(sum(row), k * max(row))
+        if B > 2 ** 63 - 1:
             break
         K = k
     return K

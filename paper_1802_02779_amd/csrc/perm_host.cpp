@@ -148,16 +148,14 @@ static int primes_needed(int n, const int64_t *a, int64_t lda) {
 }
 
 // Layers 1..K whose stored values provably lie in [-(2^63 - 1), 2^63 - 1]
-// (returns K, 0 <= K <= n): |F(S)| for |S| = k is at most
-// min(prod_{i<k} R_i, prod_{i<k} (i+1) M_i), R_i = sum_j |a_ij|,
-// M_i = max_j |a_ij| (expand along row k-1: at most R_{k-1}, and at most k
-// times M_{k-1}, times the bound of layer k-1).  Those layers can run in
-// plain 64-bit arithmetic: sums taken mod 2^64 recover a value in that range
-// exactly.
+// (returns K, 0 <= K <= n): expanding along row k - 1, |F(S)| for |S| = k is
+// at most min(R_{k-1}, k M_{k-1}) times the bound of layer k - 1, with
+// R_i = sum_j |a_ij| and M_i = max_j |a_ij| (the terms of S have at most k
+// columns).  Those layers can run in plain 64-bit arithmetic: sums taken
+// mod 2^64 recover a value in that range exactly.
 static int plain_int64_layers(int n, const int64_t *a) {
-    const u128h lim = ((u128h)1 << 63) - 1, top = ~(u128h)0;
-    auto sat_mul = [&](u128h x, u128h y) { return (x != 0 && y > top / x) ? top : x * y; };
-    u128h pr = 1, pf = 1;
+    const u128h lim = ((u128h)1 << 63) - 1;
+    u128h B = 1;
     int K = 0;
     for (int k = 1; k <= n; k++) {
         u128h R = 0, M = 0;
@@ -167,9 +165,9 @@ static int plain_int64_layers(int n, const int64_t *a) {
             R += m;
             if (m > M) M = m;
         }
-        pr = sat_mul(pr, R);
-        pf = sat_mul(pf, (u128h)k * M);
-        if ((pr < pf ? pr : pf) > lim) break;
+        const u128h kM = (u128h)k * M, f = R < kM ? R : kM;
+        if (f != 0 && B > lim / f) break;
+        B *= f;
         K = k;
     }
     return K;
