@@ -60,7 +60,7 @@ def tune_layer(perm, inputs, torch, n: int, log=_log, reps: int = 3):
     default = perm.perm_tuning_t.from_buffer_copy(base)
     default.layer_t[n] = 0
     default.layer_xcd_remap[n] = -1
-    default.layer_flags[n] = 0
+    default.layer_flags[n] = base.layer_flags[n] & ~1  # bit 0 is this sweep's; other bits are kept
     default.layer_thin[n] = 0
     perm.perm_tuning_set(default)
     run = lambda: perm.perm_solve_async(n, d_a, n, d_r, ws)  # noqa: E731
@@ -78,7 +78,7 @@ def tune_layer(perm, inputs, torch, n: int, log=_log, reps: int = 3):
                     cand = perm.perm_tuning_t.from_buffer_copy(default)
                     cand.layer_t[n] = t
                     cand.layer_xcd_remap[n] = chunk
-                    cand.layer_flags[n] = nt
+                    cand.layer_flags[n] = (default.layer_flags[n] & ~1) | nt
                     cand.layer_thin[n] = thin
                     perm.perm_tuning_set(cand)
                     ms = _time_ms(run, reps, torch.cuda.synchronize)
@@ -89,8 +89,8 @@ def tune_layer(perm, inputs, torch, n: int, log=_log, reps: int = 3):
                     if ms < best[0]:
                         best = (ms, t, chunk, nt, thin)
     final = perm.perm_tuning_t.from_buffer_copy(base)
-    (final.layer_t[n], final.layer_xcd_remap[n], final.layer_flags[n],
-     final.layer_thin[n]) = best[1], best[2], best[3], best[4]
+    (final.layer_t[n], final.layer_xcd_remap[n], final.layer_thin[n]) = best[1], best[2], best[4]
+    final.layer_flags[n] = (final.layer_flags[n] & ~1) | best[3]
     perm.perm_tuning_set(final)
     log(f"layer n={n}: default {ref_ms:.3f} ms -> t={best[1]} chunk={best[2]} nt={best[3]} "
         f"thin={best[4]} {best[0]:.3f} ms")
