@@ -68,6 +68,15 @@ def _load() -> ctypes.CDLL:
             lib.oracle_multi_c128.restype = ctypes.c_int
             lib.oracle_multi_modp.argtypes = [ctypes.c_int, ctypes.c_int, ip, up, ctypes.c_uint64, ctypes.c_int, up]
             lib.oracle_multi_modp.restype = ctypes.c_int
+            lib.oracle_ryser_modp.argtypes = [ctypes.c_int, up, ctypes.c_uint64, ctypes.c_int, up]
+            lib.oracle_ryser_modp.restype = ctypes.c_int
+            lib.oracle_mulmod_pm61.argtypes = [ctypes.c_uint64, ctypes.c_uint64, ctypes.c_uint64]
+            lib.oracle_mulmod_pm61.restype = ctypes.c_uint64
+            lib.oracle_per_gauss_modp.argtypes = [ctypes.c_int, up, up, ctypes.c_uint64, ctypes.c_int, up]
+            lib.oracle_per_gauss_modp.restype = ctypes.c_int
+            lib.oracle_per_c128_many.argtypes = [ctypes.c_int64, ip, ctypes.POINTER(ctypes.c_int64), dp,
+                                                 ctypes.c_int, dp]
+            lib.oracle_per_c128_many.restype = ctypes.c_int
             lib.oracle_max_threads.argtypes = []
             lib.oracle_max_threads.restype = ctypes.c_int
             _lib = lib
@@ -207,3 +216,112 @@ def per_multi_int(A, mult, nthreads: int = 0, redundant: int = 1) -> int:
     def g_mod(res: List[List[int]], p: int) -> int:
         return multi_modp(np.array(res, dtype=np.uint64).reshape(len(res), m), mult, p, nthreads=nthreads)
     return exact.per_multi_int_multimodular(A, mult, g_mod, redundant=redundant)
+
+
+# ------------------------------------------------ eq. (4) mod p, O(n) memory
+def ryser_modp(R, p: int, nthreads: int = 0) -> int:
+    """per(R) mod p by Ryser's eq. (4) over all 2^n column subsets in
+    Gray-code order (perm_oracle.c); R holds residues in [0, p) and
+    p = 2^61 - c with c < 2^16.  O(n) memory, so n may exceed the tables'
+    limit (up to 40; the time is 2^n * n^2 / threads)."""
+    R = np.ascontiguousarray(np.asarray(R, dtype=np.uint64))
+    if R.ndim != 2 or R.shape[0] != R.shape[1]:
+        raise ValueError("square matrix expected")
+    out = np.zeros(1, dtype=np.uint64)
+    up = ctypes.POINTER(ctypes.c_uint64)
+    rc = _load().oracle_ryser_modp(R.shape[0], R.ctypes.data_as(up), ctypes.c_uint64(p), nthreads,
+                                   out.ctypes.data_as(up))
+    _check(rc, "oracle_ryser_modp")
+    return int(out[0])
+
+
+def mulmod_pm61(x: int, y: int, p: int) -> int:
+    """The modular product the eq. (4) oracle uses (for its own pin)."""
+    return int(_load().oracle_mulmod_pm61(ctypes.c_uint64(x), ctypes.c_uint64(y), ctypes.c_uint64(p)))
+
+
+def per_int_ryser(A, nthreads: int = 0, redundant: int = 1) -> int:
+    """Exact integer permanent by eq. (4) mod primes 2^61 - c and Garner,
+    with the redundant-prime check (any order up to 40)."""
+    def per_mod(res: List[List[int]], p: int) -> int:
+        return ryser_modp(np.array(res, dtype=np.uint64).reshape(len(res), len(res)), p, nthreads=nthreads)
+    return exact.per_int_multimodular(A, per_mod, redundant=redundant)
+
+
+# ------------------------------------------- Gaussian integers, exact values
+def per_gauss_modp(X, Y, p: int, nthreads: int = 0):
+    """(Re, Im) of per(X + iY) mod p for integer matrices given as residues
+    in [0, p) (stored sub-permanents over Z[i] mod p, perm_oracle.c)."""
+    X = np.ascontiguousarray(np.asarray(X, dtype=np.uint64))
+    Y = np.ascontiguousarray(np.asarray(Y, dtype=np.uint64))
+    if X.ndim != 2 or X.shape[0] != X.shape[1] or X.shape != Y.shape:
+        raise ValueError("two square matrices of one shape expected")
+    out = np.zeros(2, dtype=np.uint64)
+    up = ctypes.POINTER(ctypes.c_uint64)
+    rc = _load().oracle_per_gauss_modp(X.shape[0], X.ctypes.data_as(up), Y.ctypes.data_as(up),
+                                       ctypes.c_uint64(p), nthreads, out.ctypes.data_as(up))
+    _check(rc, "oracle_per_gauss_modp")
+    return int(out[0]), int(out[1])
+
+
+def per_gauss_int(X, Y, nthreads: int = 0, redundant: int = 1):
+    """Exact per(X + iY) for integer matrices X, Y, as a pair of Python ints.
+
+    Both parts are bounded by prod_i sum_j (|x_ij| + |y_ij|) >= prod_i sum_j
+    |g_ij| >= |per|; primes are chosen for that bound, each part is
+    recombined by Garner and checked on the redundant prime(s)."""
+    Xi = [[int(v) for v in row] for row in np.asarray(X)]
+    Yi = [[int(v) for v in row] for row in np.asarray(Y)]
+    n = len(Xi)
+    B = 1
+    for i in range(n):
+        B *= sum(abs(Xi[i][j]) + abs(Yi[i][j]) for j in range(n))
+    ps = exact.primes_for_bound(B, redundant=redundant)
+    used = ps[: len(ps) - redundant]
+    res = []
+    for p in ps:
+        xr = np.array([[v % p for v in row] for row in Xi], dtype=np.uint64).reshape(n, n)
+        yr = np.array([[v % p for v in row] for row in Yi], dtype=np.uint64).reshape(n, n)
+        res.append(per_gauss_modp(xr, yr, p, nthreads=nthreads))
+    re = exact.garner([r[0] for r in res[: len(used)]], used)
+    im = exact.garner([r[1] for r in res[: len(used)]], used)
+    for (a, b), p in zip(res[len(used):], ps[len(used):]):
+        if re % p != a or im % p != b:
+            raise ArithmeticError("redundant prime disagrees with recombined value")
+    return re, im
+
+
+def per_dyadic_exact(A, bits: int, nthreads: int = 0):
+    """Exact per(A) of a complex matrix whose parts are integer multiples of
+    2^-bits: per(A) = 2^(-n bits) per(2^bits A), the latter over Z[i].
+    Returns (Re, Im) as fractions.Fraction."""
+    from fractions import Fraction
+    A = _as_c128(A)
+    n = A.shape[0]
+    q = float(2 ** bits)
+    X = A.real * q
+    Y = A.imag * q
+    if not (np.all(X == np.round(X)) and np.all(Y == np.round(Y))):
+        raise ValueError("entries are not multiples of 2^-bits")
+    re, im = per_gauss_int(X.astype(np.int64), Y.astype(np.int64), nthreads=nthreads)
+    s = Fraction(1, 2 ** (n * bits))
+    return re * s, im * s
+
+
+# ----------------------------------------------- many small complex matrices
+def per_c128_many(ns, offsets, mats, nthreads: int = 0) -> np.ndarray:
+    """per_c128 (paper's memo order) of every matrix of a packed batch:
+    matrix i has order ns[i] <= 20 and starts at complex element offsets[i]
+    of mats.  Returns complex128[count]."""
+    ns = np.ascontiguousarray(np.asarray(ns, dtype=np.int32))
+    offsets = np.ascontiguousarray(np.asarray(offsets, dtype=np.int64))
+    mats = np.ascontiguousarray(np.asarray(mats, dtype=np.complex128))
+    count = int(ns.shape[0])
+    out = np.zeros(count, dtype=np.complex128)
+    dp = ctypes.POINTER(ctypes.c_double)
+    rc = _load().oracle_per_c128_many(count, ns.ctypes.data_as(ctypes.POINTER(ctypes.c_int32)),
+                                      offsets.ctypes.data_as(ctypes.POINTER(ctypes.c_int64)),
+                                      mats.view(np.float64).ctypes.data_as(dp), nthreads,
+                                      out.view(np.float64).ctypes.data_as(dp))
+    _check(rc, "oracle_per_c128_many")
+    return out

@@ -563,3 +563,216 @@ int oracle_multi_modp(int n, int m, const int32_t *mult, const uint64_t *r, uint
     free(ks);
     return 0;
 }
+
+/* ------------------------------------------------- eq. (4) mod p, O(n) memory */
+/*
+ * Ryser's formula (eq. 4 of the paper, section 3.3) in exact modular
+ * arithmetic, for orders beyond the reach of the 2^n tables above:
+ *
+ *     per(A) = (-1)^n  sum over column subsets S of (-1)^|S| prod_i r_i(S),
+ *     r_i(S) = sum_{j in S} a_ij.
+ *
+ * Everything is reduced mod a prime p = 2^61 - c (1 <= c < 2^16), so the
+ * result is exact mod p; Garner on several primes gives the integer.  The
+ * subsets are visited in binary-reflected Gray-code order (the g-th subset is
+ * g XOR (g >> 1); going from g-1 to g flips exactly the column ctz(g)), so
+ * each step changes every row sum by one entry.  The 2^n codes are cut into
+ * blocks; a block forms the row sums of its first subset directly.  Memory is
+ * O(n) per thread.  This is an independent method from the stored minors
+ * above: it shares no step with them.
+ *
+ * Multiplication mod p = 2^61 - c (the classical pseudo-Mersenne
+ * reduction): z = x*y < 2^122 is written z = hi*2^61 + lo, and
+ * 2^61 = c (mod p), so z = lo + c*hi (mod p); twice, then subtract p while
+ * the value is >= p.
+ */
+#define ORACLE_RYSER_N_MAX 40
+
+static uint64_t mulmod_pm61(uint64_t x, uint64_t y, uint64_t p, uint64_t c)
+{
+    const uint64_t m61 = ((uint64_t)1 << 61) - 1;
+    u128 z = (u128)x * y;                       /* < 2^122 */
+    u128 w = (z >> 61) * c + (uint64_t)(z & m61); /* < 2^61 * 2^16 + 2^61 */
+    uint64_t v = (uint64_t)(w & m61) + (uint64_t)(w >> 61) * c; /* < 2^61 + 2^33 */
+    while (v >= p)
+        v -= p;
+    return v;
+}
+
+static uint64_t addmod(uint64_t x, uint64_t y, uint64_t p) { uint64_t s = x + y; return s >= p ? s - p : s; }
+static uint64_t submod(uint64_t x, uint64_t y, uint64_t p) { return x >= y ? x - y : x + p - y; }
+
+/* x * y mod p, exposed so a test can check the reduction against exact
+ * integer arithmetic. */
+uint64_t oracle_mulmod_pm61(uint64_t x, uint64_t y, uint64_t p)
+{
+    return mulmod_pm61(x, y, p, ((uint64_t)1 << 61) - p);
+}
+
+/* a: n x n residues in [0, p), row-major; p = 2^61 - c with 1 <= c < 2^16. */
+int oracle_ryser_modp(int n, const uint64_t *a, uint64_t p, int nthreads, uint64_t *out)
+{
+    const uint64_t two61 = (uint64_t)1 << 61;
+    if (n < 0 || n > ORACLE_RYSER_N_MAX || !out || (n > 0 && !a) || p >= two61 || two61 - p >= (1u << 16))
+        return -1;
+    for (size_t i = 0; i < (size_t)n * n; i++)
+        if (a[i] >= p)
+            return -1;
+    if (n == 0) {
+        *out = 1;
+        return 0;
+    }
+    const uint64_t c = two61 - p;
+    const int bb = n < 16 ? n : 16;          /* codes per block: 2^bb */
+    const int64_t blocks = (int64_t)1 << (n - bb);
+    uint64_t pos = 0, neg = 0;               /* sums of terms with sign + and - */
+#ifdef _OPENMP
+    if (nthreads > 0)
+        omp_set_num_threads(nthreads);
+#endif
+#pragma omp parallel
+    {
+        uint64_t r[ORACLE_RYSER_N_MAX];
+        uint64_t my_pos = 0, my_neg = 0;
+#pragma omp for schedule(dynamic, 1)
+        for (int64_t blk = 0; blk < blocks; blk++) {
+            const uint64_t g0 = (uint64_t)blk << bb;
+            uint64_t S = g0 ^ (g0 >> 1);
+            for (int i = 0; i < n; i++) {
+                uint64_t s = 0;
+                for (int j = 0; j < n; j++)
+                    if ((S >> j) & 1u)
+                        s = addmod(s, a[(size_t)i * n + j], p);
+                r[i] = s;
+            }
+            for (uint64_t g = g0; g < g0 + ((uint64_t)1 << bb); g++) {
+                if (g != g0) {
+                    const int col = __builtin_ctzll(g);
+                    S ^= (uint64_t)1 << col;
+                    if ((S >> col) & 1u)
+                        for (int i = 0; i < n; i++) r[i] = addmod(r[i], a[(size_t)i * n + col], p);
+                    else
+                        for (int i = 0; i < n; i++) r[i] = submod(r[i], a[(size_t)i * n + col], p);
+                }
+                /* prod_i r_i: two interleaved chains (even and odd rows) */
+                uint64_t e = 1, o = 1;
+                int i = 0;
+                for (; i + 1 < n; i += 2) {
+                    e = mulmod_pm61(e, r[i], p, c);
+                    o = mulmod_pm61(o, r[i + 1], p, c);
+                }
+                if (i < n)
+                    e = mulmod_pm61(e, r[i], p, c);
+                const uint64_t term = mulmod_pm61(e, o, p, c);
+                /* sign (-1)^(n - |S|) */
+                if (((n - __builtin_popcountll(S)) & 1) == 0)
+                    my_pos = addmod(my_pos, term, p);
+                else
+                    my_neg = addmod(my_neg, term, p);
+            }
+        }
+#pragma omp critical
+        {
+            pos = addmod(pos, my_pos, p);
+            neg = addmod(neg, my_neg, p);
+        }
+    }
+    *out = submod(pos, neg, p);
+    return 0;
+}
+
+/* -------------------------------------------- Gaussian integers mod p (exact) */
+/*
+ * The stored sub-permanents of section 4 for a matrix of Gaussian integers
+ * g_ij = x_ij + i y_ij, reduced mod a prime p < 2^61: every value is a pair
+ * (re, im) of residues, and a product follows (x + iy)(u + iv) =
+ * (xu - yv) + i(xv + yu).  Sums are exact 128-bit integers (at most 40
+ * products below 2^122 per part) reduced once per stored value.  With
+ * A = 2^-b G (a dyadic complex matrix), per(A) = 2^-nb per(G) exactly, so
+ * Garner over enough primes gives the exact permanent of A and hence the
+ * true rounding error of any fp64 evaluation.  Layers mode, OpenMP.
+ */
+#define ORACLE_GAUSS_N_MAX 26
+
+int oracle_per_gauss_modp(int n, const uint64_t *re, const uint64_t *im, uint64_t p, int nthreads,
+                          uint64_t *out)
+{
+    if (n < 0 || n > ORACLE_GAUSS_N_MAX || !out || (n > 0 && (!re || !im)) || p < 2 ||
+        p >= ((uint64_t)1 << 61))
+        return -1;
+    for (size_t i = 0; i < (size_t)n * n; i++)
+        if (re[i] >= p || im[i] >= p)
+            return -1;
+    if (n == 0) {
+        out[0] = 1 % p;
+        out[1] = 0;
+        return 0;
+    }
+    size_t N = (size_t)1 << n;
+    uint64_t *tab = (uint64_t *)malloc(2 * N * sizeof(uint64_t));
+    if (!tab)
+        return -2;
+    for (int j = 0; j < n; j++) {
+        tab[2 * ((size_t)1 << j)] = re[j];
+        tab[2 * ((size_t)1 << j) + 1] = im[j];
+    }
+#ifdef _OPENMP
+    if (nthreads > 0)
+        omp_set_num_threads(nthreads);
+#endif
+    for (int k = 2; k <= n; k++) {
+        const uint64_t *xr = re + (size_t)(k - 1) * n, *yr = im + (size_t)(k - 1) * n;
+#pragma omp parallel for schedule(static, 4096)
+        for (int64_t S = 0; S < (int64_t)N; S++) {
+            if (popcount32((uint32_t)S) != k)
+                continue;
+            /* re = sum x*u - sum y*v, im = sum x*v + sum y*u */
+            u128 xu = 0, yv = 0, xv = 0, yu = 0;
+            for (int j = 0; j < n; j++) {
+                if (!((S >> j) & 1))
+                    continue;
+                const size_t P = (size_t)(S & ~((int64_t)1 << j));
+                const uint64_t u = tab[2 * P], v = tab[2 * P + 1];
+                xu += (u128)xr[j] * u;
+                yv += (u128)yr[j] * v;
+                xv += (u128)xr[j] * v;
+                yu += (u128)yr[j] * u;
+            }
+            const uint64_t a1 = (uint64_t)(xu % p), a2 = (uint64_t)(yv % p);
+            tab[2 * S] = a1 >= a2 ? a1 - a2 : a1 + p - a2;
+            tab[2 * S + 1] = (uint64_t)((xv % p + yu % p) % p);
+        }
+    }
+    out[0] = tab[2 * (N - 1)];
+    out[1] = tab[2 * (N - 1) + 1];
+    free(tab);
+    return 0;
+}
+
+/* ------------------------------------------------ many small complex matrices */
+/*
+ * oracle_per_c128 (memo mode, the paper's order) for each of `count`
+ * matrices packed row-major back to back: matrix i has order ns[i] <= 20
+ * and starts at complex element offsets[i] of mats; out[2i], out[2i+1] get
+ * its permanent.  OpenMP over the matrices (each one single-threaded).
+ */
+int oracle_per_c128_many(int64_t count, const int32_t *ns, const int64_t *offsets, const double *mats,
+                         int nthreads, double *out)
+{
+    if (count < 0 || (count > 0 && (!ns || !offsets || !mats || !out)))
+        return -1;
+    for (int64_t i = 0; i < count; i++)
+        if (ns[i] < 0 || ns[i] > 20 || offsets[i] < 0)
+            return -1;
+    int bad = 0;
+#ifdef _OPENMP
+    if (nthreads > 0)
+        omp_set_num_threads(nthreads);
+#endif
+#pragma omp parallel for schedule(dynamic, 256) reduction(| : bad)
+    for (int64_t i = 0; i < count; i++) {
+        if (oracle_per_c128(ns[i], mats + 2 * offsets[i], 0, 1, out + 2 * i) != 0)
+            bad = 1;
+    }
+    return bad ? -2 : 0;
+}

@@ -17,6 +17,21 @@ Entries (inputs are regenerated from the seeds by the tests):
   multi_int_n36_M18_bern_s0
                    the same counts with a 36 x m Bernoulli(1/2) block
                    (first m columns of bernoulli01(36, seed 0)), exact
+  c128_n{23,24,25,27,29,30}_s0
+                   complex Gaussian of every order the shipped tuning table
+                   treats separately (n = 30 needs about 26 GB of host RAM)
+  int_n{25,27,29}_bern_s0
+                   Bernoulli(1/2) 0/1 matrices, exact (stored minors mod p)
+  int_n{31,32,33,34}_bern_s0
+                   Bernoulli(1/2) 0/1 matrices beyond the tables' reach,
+                   exact by eq. (4) mod p (O(n) memory; n = 34 takes about
+                   half an hour on 8 cores)
+  batch_2p20_s2018_s1
+                   the timed batch (2^20 submatrices of order 3..12 of the
+                   seeded 64x64 Haar unitary, submatrix_batch seed 1):
+                   SHA-256 of all oracle results as little-endian
+                   complex128, and one digest per order (results of that
+                   order in batch order)
 Complex values are stored as the IEEE-754 bit patterns of the oracle's fp64
 FMA chain, plus the oracle's per(|A|) for the relative tolerance.
 """
@@ -63,6 +78,21 @@ def multi_int_entry(n, M, seed, threads):
     return {"value": str(native.per_multi_int(B, t, nthreads=threads)), "mult": [int(x) for x in t]}
 
 
+def batch_digest_entry(threads):
+    import hashlib
+    U = inputs.haar_unitary(64, seed=2018)
+    b = inputs.submatrix_batch(U, 1 << 20, 3, 12, seed=1)
+    t0 = time.time()
+    z = native.per_c128_many(b.ns, b.offsets, b.mats, nthreads=threads)
+    raw = np.ascontiguousarray(z).astype("<c16").tobytes()
+    per_order = {}
+    for n in range(3, 13):
+        sel = np.ascontiguousarray(z[b.ns == n]).astype("<c16").tobytes()
+        per_order[str(n)] = hashlib.sha256(sel).hexdigest()
+    return {"count": int(b.count), "sha256": hashlib.sha256(raw).hexdigest(), "sha256_by_order": per_order,
+            "oracle_seconds": round(time.time() - t0, 2)}
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--threads", type=int, default=0)
@@ -85,7 +115,18 @@ def main():
         ("multi_c128_n36_M18_s0", lambda: multi_c128_entry(36, 18, 0, args.threads)),
         ("multi_c128_n40_M20_s0", lambda: multi_c128_entry(40, 20, 0, args.threads)),
         ("multi_int_n36_M18_bern_s0", lambda: multi_int_entry(36, 18, 0, args.threads)),
+        ("batch_2p20_s2018_s1", lambda: batch_digest_entry(args.threads)),
     ]
+    for n in (23, 24, 25, 27, 29, 30):
+        jobs.append(("c128_n%d_s0" % n, lambda n=n: c128_entry(inputs.complex_gaussian(n, seed=0), args.threads)))
+    for n in (25, 27, 29):
+        jobs.append(("int_n%d_bern_s0" % n,
+                     lambda n=n: {"value": str(native.per_int(inputs.bernoulli01(n, seed=0), nthreads=args.threads))}))
+    for n in (31, 32, 33, 34):
+        jobs.append(("int_n%d_bern_s0" % n,
+                     lambda n=n: {"value": str(native.per_int_ryser(inputs.bernoulli01(n, seed=0),
+                                                                    nthreads=args.threads)),
+                                  "method": "eq. (4) mod p"}))
     for key, fn in jobs:
         if args.only and args.only not in key:
             continue
