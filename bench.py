@@ -102,6 +102,11 @@ def source_hash() -> str:
     return _h(ROOT)
 
 
+def int_source_hash() -> str:
+    from paper_1802_02779_amd.profiling import int_source_hash as _h
+    return _h(ROOT)
+
+
 def bits(z):
     import numpy as np
     return tuple(int(x) for x in np.array([z.real, z.imag], dtype=np.float64).view(np.uint64))
@@ -185,21 +190,35 @@ def main():
     torch.cuda.synchronize()
     prof = perm.perm_profile_read()
     perm.perm_profile_enable(False)
-    launches = int(prof.layer_c128_launches)
-    avg_ms = prof.layer_c128_ms / max(launches, 1)
-    bytes_per_launch = layer_bytes(n) / (n - 1)
+    # the sweep the shipped tuning picks for n = 28: the block sweep (one
+    # launch per high level) or the layer sweep (one launch per layer)
+    if prof.block_c128_launches:
+        kernel, launches, kern_ms = "k_block_c128", int(prof.block_c128_launches), prof.block_c128_ms
+        counters_file = os.path.join(ROOT, "profiles", "block_c128_n28_counters.json")
+    else:
+        kernel, launches, kern_ms = "k_layer_c128", int(prof.layer_c128_launches), prof.layer_c128_ms
+        counters_file = COUNTERS
+    per_step = launches // args.steps
+    avg_ms = kern_ms / max(launches, 1)
+    # algorithmic bytes of one solve (every stored value written once and
+    # read once), shared equally by the launches of a step
+    bytes_per_launch = layer_bytes(n) / per_step
     achieved = bytes_per_launch / (avg_ms * 1e-3) / 1e9
     flops_per_step = algorithmic_flops(n)
-    kern_ms_per_step = prof.layer_c128_ms / args.steps
+    kern_ms_per_step = kern_ms / args.steps
     traffic = None
-    if os.path.exists(COUNTERS):
-        with open(COUNTERS) as f:
+    if os.path.exists(counters_file):
+        with open(counters_file) as f:
             cnt = json.load(f)
         if cnt.get("source_hash") == source_hash():
             traffic = cnt.get("hbm_bytes_per_launch")
-    roofline = {"bound": "hbm", "kernel": "k_layer_c128", "achieved": round(achieved, 1),
+    roofline = {"bound": "hbm", "kernel": kernel, "achieved": round(achieved, 1),
                 "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
-                "traffic": traffic, "avg_launch_ms": round(avg_ms, 5), "launches_per_step": n - 1,
+                "traffic": traffic,
+                "traffic_source": os.path.relpath(counters_file, ROOT) + " (rocprofv3 FETCH_SIZE + WRITE_SIZE, "
+                                  "valid while the kernel sources and tuning row hash to its source_hash; "
+                                  "null otherwise)",
+                "avg_launch_ms": round(avg_ms, 5), "launches_per_step": per_step,
                 "algorithmic_bytes_per_launch": int(bytes_per_launch),
                 "fp64_tflops": round(flops_per_step / (kern_ms_per_step * 1e-3) / 1e12, 3),
                 "fp64_frac": round(flops_per_step / (kern_ms_per_step * 1e-3) / 1e12 / FP64_PEAK_TFLOPS, 4)}
@@ -222,7 +241,7 @@ def main():
     if traffic:
         roofline["traffic_gbs"] = round(traffic / (avg_ms * 1e-3) / 1e9, 1)
         roofline["amplification"] = round(traffic / bytes_per_launch, 3)
-    log(f"layer sweep: avg {avg_ms:.4f} ms/launch, {achieved:.0f} GB/s algorithmic; "
+    log(f"{kernel}: avg {avg_ms:.4f} ms/launch, {achieved:.0f} GB/s algorithmic; "
         f"measured traffic at {roofline.get('traffic_gbs')} GB/s, plain 1 GiB copy {copy_gbs:.0f} GB/s")
 
     result = {
@@ -434,12 +453,54 @@ def _extra_int30(perm, inputs, golden, log, out):
         ts.append((time.perf_counter() - t0) * 1000.0)
     ms = sorted(ts)[2]  # median of 5
     g = golden.get("int_n30_bern_s0")
-    K = plain_layers(B)
-    out["int_n30_bernoulli"] = {"ms": round(ms, 3), "value": str(v),
-                                "verified": (str(v) == g["value"]) if g else None,
-                                "plain_int64_layers": K, "residues": 3,
-                                "hbm_bytes": int_layer_bytes(30, K, 3)}
-    log(f"n=30 0/1 integer: {ms:.2f} ms")
+    # the library's own count of plain 64-bit layers, and the layer kernels'
+    # time, from its event profile
+    perm.perm_profile_enable(True)
+    perm.perm_profile_read()
+    for _ in range(3):
+        perm.perm_solve(B, workspace=wsi)
+    pr = perm.perm_profile_read()
+    perm.perm_profile_enable(False)
+    K = int(pr.int_plain_layers) // 3 + 1
+    launches = int(pr.layer_modp_launches) // 3
+    kern_ms = pr.layer_modp_ms / 3
+    algo = int_layer_bytes(30, K, 3)
+    achieved = algo / (kern_ms * 1e-3) / 1e9
+    traffic = None
+    cfile = os.path.join(ROOT, "profiles", "layer_modp_n30_counters.json")
+    if os.path.exists(cfile):
+        with open(cfile) as f:
+            cnt = json.load(f)
+        if cnt.get("source_hash") == int_source_hash():
+            traffic = cnt.get("hbm_bytes_per_launch")
+    # the per-term arithmetic: every row of a 0/1 matrix is binary, so every
+    # nonzero term is one addition (64-bit on the plain layers, 128-bit per
+    # prime on the residue layers); its rate from the probe on the same GPU
+    mac_fold, add64 = perm.perm_probe_int()
+    plain_terms = resid_terms = 0
+    for k in range(2, 31):
+        terms = int(B[k - 1].sum()) * math.comb(29, k - 1)
+        if k <= K:
+            plain_terms += terms
+        else:
+            resid_terms += 3 * terms
+    alu_ms = (plain_terms + 2 * resid_terms) / (add64 * 1e9) * 1e3
+    out["int_n30_bernoulli"] = {
+        "ms": round(ms, 3), "value": str(v), "verified": (str(v) == g["value"]) if g else None,
+        "plain_int64_layers": K, "residues": 3, "hbm_bytes": algo,
+        "roofline": {"bound": "hbm", "kernel": "k_layer_modp", "achieved": round(achieved, 1),
+                     "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
+                     "traffic": traffic, "launches_per_solve": launches,
+                     "avg_launch_ms": round(kern_ms / max(launches, 1), 5),
+                     "algorithmic_bytes_per_launch": int(algo / max(launches, 1)),
+                     "traffic_source": "profiles/layer_modp_n30_counters.json"},
+        "alu": {"probe_add64_gops": round(add64, 1), "probe_mac128_fold_gops": round(mac_fold, 1),
+                "plain_add_terms": plain_terms, "residue_add_terms": resid_terms,
+                "floor_ms": round(alu_ms, 3), "frac": round(alu_ms / kern_ms, 4),
+                "note": "128-bit additions counted as two 64-bit ones; the sweep's time goes to index "
+                        "work and memory, not to this arithmetic"}}
+    log(f"n=30 0/1 integer: {ms:.2f} ms, layer kernels {kern_ms:.2f} ms, {achieved:.0f} GB/s algorithmic; "
+        f"ALU floor {alu_ms:.3f} ms (add64 probe {add64:.0f} G/s)")
     del wsi
 
 
@@ -736,7 +797,21 @@ def cpu_baseline(inputs, log):
     m28, a28 = 28 * (2 ** 27 - 1), 26 * 2 ** 27 + 1
     paper = {mach: round(exact.machine_time_ms(m28, a28, mach) / 86400e3, 1) for mach in ("ENIAC", "TRADIC")}
     log(f"paper's rate model, n=28 Store-zechin: ENIAC {paper['ENIAC']} days, TRADIC {paper['TRADIC']} days")
+    model = "unknown"
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    model = line.split(":", 1)[1].strip()
+                    break
+    except OSError:
+        pass
+    try:
+        usable = len(os.sched_getaffinity(0))
+    except (AttributeError, OSError):
+        usable = os.cpu_count()
     return {"value": round(1.0 / dt, 5), "unit": "perms/s", "cores": cores, "kind": "oracle",
+            "host_cpu_model": model, "host_cpus_usable": usable,
             "paper_rate_model_n28_days": paper,
             "sample": "one full 28x28 complex128 permanent (all 2^28 stored sub-permanents), "
                       f"{dt:.1f} s wall",

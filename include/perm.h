@@ -219,6 +219,26 @@ int perm_solve_multi(perm_dtype_t dt, int n, int m, const int32_t *mult, const v
 int perm_solve_multi_async(int n, int m, const int32_t *mult, const perm_c128_t *a_dev, int64_t lda,
                            perm_c128_t *result_dev, void *workspace, size_t ws_bytes, void *stream);
 
+/* Repeated rows and columns: the permanent of the n x n matrix in which row i
+ * of the r x c host matrix a (row-major, lda >= c) is repeated row_mult[i]
+ * times and column j col_mult[j] times (every multiplicity >= 1, both sums
+ * equal n): the amplitude, up to 1 / sqrt(prod row_mult! prod col_mult!), of
+ * bosons entering r modes and leaving c modes with those occupations
+ * (section 2).  per(A) = per(A^T) (property 1 of section 3.1), so one side is
+ * expanded and the other compressed into count vectors, and the call runs
+ * perm_solve_multi on the result.  The side compressed is the one with fewer
+ * count vectors, prod(mult + 1) compared exactly (ties compress the
+ * columns); the orientation also fixes the fp64 chain, so a complex result
+ * is a deterministic function of the inputs (perm_bunched_orientation
+ * reports it: *rows = 1 when the rows are compressed).
+ * perm_bunched_workspace_bytes: device workspace of that perm_solve_multi
+ * call (0 for invalid arguments).  Result and errors as perm_solve_multi;
+ * PERM_EINVAL also when the sums differ. */
+size_t perm_bunched_workspace_bytes(perm_dtype_t dt, int r, const int32_t *row_mult, int c, const int32_t *col_mult);
+int perm_bunched_orientation(int r, const int32_t *row_mult, int c, const int32_t *col_mult, int *rows);
+int perm_solve_bunched(perm_dtype_t dt, int r, const int32_t *row_mult, int c, const int32_t *col_mult, const void *a,
+                       int64_t lda, void *result, void *workspace, size_t ws_bytes, void *stream);
+
 /* Shape of the repeated-column plan for (n, m, mult), built on the host (no
  * device needed).  With check != 0 the plan is also verified against the
  * closed-form colex ranking of count vectors: the tiles of each layer must
@@ -248,11 +268,25 @@ int perm_multi_plan_info(int n, int m, const int32_t *mult, int check, perm_mult
  * PERM_EINVAL for a null pointer, PERM_EDEVICE on a HIP failure. */
 int perm_probe_fp64(double *tflops, void *stream);
 
+/* Measurement probe for the exact integer sweep: the rate (terms per second,
+ * in units of 1e9) of its per-term arithmetic on independent chains --
+ * mac_fold_gops: a 64 x 64 -> 128-bit product added into a 128-bit sum, the
+ * sum folded mod 2^61 - 1 after every 16 terms (the residue layers);
+ * add64_gops: a 64-bit addition (0/1 rows, plain 64-bit layers).  Runs a few
+ * ms of work on `stream`, synchronizes it, allocates and frees a small
+ * device buffer.  PERM_EINVAL for a null pointer, PERM_EDEVICE on a HIP
+ * failure. */
+int perm_probe_int(double *mac_fold_gops, double *add64_gops, void *stream);
+
 /* Device workspace bytes for a batch (host array ns of `count` orders). */
 size_t perm_batch_workspace_bytes(perm_dtype_t dt, int count, const int32_t *ns);
 
 /* Many independent permanents of orders 0..PERM_BATCH_N_MAX in one
- * persistent launch: the matrices are dealt to workgroups from a work list
+ * persistent launch.  The paper's workload (section 2) is the boson-sampling
+ * amplitude: one permanent of an n x n submatrix of the interferometer's
+ * unitary per output pattern, so a sampler needs very many small ones; the
+ * paper evaluates one at a time (sections 4-5), the batching is this
+ * library's.  The matrices are dealt to workgroups from a work list
  * sorted by cost (largest first); each workgroup keeps a matrix's whole table
  * of stored sub-permanents on chip.
  *   ns[count]      host, orders.
@@ -274,6 +308,12 @@ int perm_solve_batch(perm_dtype_t dt, int count, const int32_t *ns, const int64_
                      void *stream, uint32_t flags);
 
 /* ------------------------------------------------------------ server --- */
+/* Continuous batching of single permanents (not in the paper, which
+ * evaluates one permanent at a time): requests of mixed order arrive while
+ * others run and are admitted by the footprint of their table of stored
+ * sub-permanents (16 * 2^n bytes: section 4 stores every minor once); small
+ * orders share launches of the batched kernel, large ones run the layer
+ * sweep on their own streams. */
 
 typedef struct perm_server perm_server_t;
 
@@ -326,7 +366,12 @@ int perm_server_destroy(perm_server_t *s);
  *                      consecutive tiles; 0 = hardware order, -1 = default.
  *   layer_flags[n]     bit 0: non-temporal stores of layer outputs;
  *                      bit 1: the exact integer sweep's plain 64-bit layers
- *                      (those bounded below 2^63) use layer_t + 1 low columns.
+ *                      (those bounded below 2^63) use layer_t + 1 low columns;
+ *                      bit 2: complex orders 24..32 run the block sweep
+ *                      instead of the layer sweep: one workgroup per high
+ *                      part T holds F(T u L) for all 2^t low parts L (t =
+ *                      min(layer_t, 13)), one launch per |T|; same values,
+ *                      same chains, same bits.
  *   layer_thin[n]      tiles with fewer outputs than this are computed one
  *                      output per thread instead of staging a window in LDS;
  *                      0 = library default (128), -1 = never.
@@ -368,6 +413,11 @@ typedef struct {
     int64_t multi_c128_launches;
     double multi_modp_ms;   /* the same, residues */
     int64_t multi_modp_launches;
+    double block_c128_ms;   /* complex block sweep (layer_flags bit 2), per high-level launch */
+    int64_t block_c128_launches;
+    int64_t int_plain_layers; /* layers of perm_solve's exact integer sweep run in plain
+                                 64-bit arithmetic (counted once per run of the plain
+                                 prefix, which serves every prime) */
 } perm_profile_t;
 
 int perm_profile_enable(int on);

@@ -385,6 +385,7 @@ struct ProfEv {
 };
 static std::vector<ProfEv> g_prof_events;
 static std::vector<hipEvent_t> g_prof_pool;
+static int64_t g_prof_plain_layers = 0;
 
 bool profiling_on() { return g_prof_on.load(std::memory_order_relaxed); }
 
@@ -405,6 +406,11 @@ void profile_record(int kind, hipEvent_t a, hipEvent_t b) {
     g_prof_events.push_back({kind, a, b});
 }
 
+void profile_count_plain(int layers) {
+    std::lock_guard<std::mutex> lk(g_prof_mu);
+    g_prof_plain_layers += layers;
+}
+
 // ------------------------------------------------------- complex solve
 static size_t align256(size_t x) { return (x + 255) & ~(size_t)255; }
 
@@ -414,13 +420,34 @@ static size_t max_layer(int n) {
     return m;
 }
 
+// Block sweep (perm_block_c128.hip): orders it serves and its low columns.
+constexpr int kBlockNMin = 24, kBlockNMax = 32, kBlockTMax = 13;
+
+static size_t block_level_bytes(int n, int t) {
+    const int nh = n - t;
+    return align256((size_t)binom_host(nh, nh / 2) * ((size_t)1 << t) * 16);
+}
+
+// Low columns of the block sweep for order n, 0 when it does not apply.
+static int block_t(int n) {
+    if (n < kBlockNMin || n > kBlockNMax || !(tuned_layer_flags(n) & 4)) return 0;
+    int t = tuned_layer_t(n);
+    if (t > kBlockTMax) t = kBlockTMax;
+    if (n - t > kHighBits) return 0;
+    return t;
+}
+
 size_t c128_workspace_bytes(int n) {
     if (n < 2) return 256;
-    return align256((size_t)n * n * 16) + 256 + 2 * align256(max_layer(n) * 16);
+    size_t tables = 2 * align256(max_layer(n) * 16);
+    if (n >= kBlockNMin && n <= kBlockNMax)  // whichever sweep and low-column count the tuning picks
+        for (int t = std::max(1, n - kHighBits); t <= std::min(kBlockTMax, n); t++)
+            tables = std::max(tables, 2 * block_level_bytes(n, t));
+    return align256((size_t)n * n * 16) + 256 + tables;
 }
 
 int solve_c128_device(int n, const void *a_dev, int64_t lda, void *result_dev, void *ws,
-                      size_t ws_bytes, hipStream_t s) {
+                      size_t ws_bytes, hipStream_t s, bool allow_profile) {
     if (n == 0) {
         static const perm_c128_t one = {1.0, 0.0};
         HIPCALL(hipMemcpyAsync(result_dev, &one, sizeof one, hipMemcpyHostToDevice, s), "hipMemcpyAsync");
@@ -446,7 +473,7 @@ int solve_c128_device(int n, const void *a_dev, int64_t lda, void *result_dev, v
             mat = packed;
         }
         hipEvent_t e0 = nullptr, e1 = nullptr;
-        const bool prof = profiling_on();
+        const bool prof = allow_profile && profiling_on();
         if (prof) {
             e0 = profile_event();
             e1 = profile_event();
@@ -459,6 +486,35 @@ int solve_c128_device(int n, const void *a_dev, int64_t lda, void *result_dev, v
         }
         return PERM_OK;
     }
+    const int tb = block_t(n);
+    if (tb) {
+        // block sweep: one launch per high level m, ping-pong by level
+        char *buf0 = base + align256((size_t)n * n * 16) + 256;
+        char *buf1 = buf0 + block_level_bytes(n, tb);
+        HIPCALL(launch_pack_c128(a_dev, lda, n, packed, buf1, s), "pack kernel");
+        const int chunk = tuned_layer_remap(n);
+        const bool prof = allow_profile && profiling_on();
+        char *cur = buf0;
+        for (int m = 0; m <= n - tb; m++) {
+            BlockArgs args;
+            plan_block(n, tb, m, chunk, &args);
+            cur = (m & 1) ? buf1 : buf0;
+            const char *prv = (m & 1) ? buf0 : buf1;
+            hipEvent_t e0 = nullptr, e1 = nullptr;
+            if (prof) {
+                e0 = profile_event();
+                e1 = profile_event();
+                if (e0) (void)hipEventRecord(e0, s);
+            }
+            HIPCALL(launch_block_c128(prv, cur, packed, args, s), "block kernel");
+            if (prof && e0 && e1) {
+                (void)hipEventRecord(e1, s);
+                profile_record(6, e0, e1);
+            }
+        }
+        HIPCALL(launch_block_readout_c128(cur, tb, result_dev, s), "readout kernel");
+        return PERM_OK;
+    }
     const size_t lay = align256(max_layer(n) * 16);
     char *buf0 = base + align256((size_t)n * n * 16) + 256;
     char *buf1 = buf0 + lay;
@@ -466,7 +522,7 @@ int solve_c128_device(int n, const void *a_dev, int64_t lda, void *result_dev, v
     const int t = tuned_layer_t(n);
     const int chunk = tuned_layer_remap(n);
     const int nt = tuned_layer_flags(n) & 1;
-    const bool prof = profiling_on();
+    const bool prof = allow_profile && profiling_on();
     char *prev = buf0, *next = buf1;
     for (int k = 2; k <= n; k++) {
         LayerArgs args;
@@ -583,16 +639,36 @@ static int solve_int(int n, const int64_t *a, int64_t lda, perm_int_t *out, void
         }
         return PERM_OK;
     };
+    // With more primes than one sweep carries, the plain layer K is kept for
+    // the later groups in the tail of buf1's last plane, when the residue
+    // layers (at most max_{k >= K} C(n, k) entries of a plane) and the
+    // conversion leave that tail untouched; the plain layers then run once.
+    uint64_t *keep = nullptr;
+    if (K >= 2 && Rt > rp && rp >= 2) {
+        size_t after = 0;
+        for (int k = K; k <= n; k++) after = std::max<size_t>(after, binom_host(n, k));
+        if (after + n + binom_host(n, K) <= plane)
+            keep = buf1 + (size_t)(rp - 1) * plane + (plane - binom_host(n, K));
+    }
     for (int s0 = 0; s0 < Rt; s0 += rp) {
         const int cnt = std::min(rp, Rt - s0);
         uint64_t *prev = buf0, *next = buf1;
         int k0 = 2;
-        if (K >= 2) {
+        if (K >= 2 && keep && s0 > 0) {
+            HIPCALL(launch_int64_to_modp(keep, prev, plane, binom_host(n, K), d_primes + s0, cnt, s),
+                    "int64 to residues kernel");
+            HIPCALL(launch_reduce_modp(d_a, n, d_primes + s0, cnt, d_red, next, plane, s), "reduce kernel");
+            k0 = K + 1;
+        } else if (K >= 2) {
             HIPCALL(launch_reduce_modp(d_a, n, d_plain, 1, d_red, prev, plane, s), "reduce kernel");
             for (int k = 2; k <= K; k++) {
                 if ((rc = layer(prev, next, k, d_plain, 1, t_plain)) != PERM_OK) return rc;
                 std::swap(prev, next);
             }
+            if (prof) profile_count_plain(K - 1);
+            if (keep)
+                HIPCALL(hipMemcpyAsync(keep, prev, (size_t)binom_host(n, K) * 8, hipMemcpyDeviceToDevice, s),
+                        "keep plain layer");
             HIPCALL(launch_int64_to_modp(prev, next, plane, binom_host(n, K), d_primes + s0, cnt, s),
                     "int64 to residues kernel");
             std::swap(prev, next);
@@ -1247,7 +1323,7 @@ int perm_tuning_set(const perm_tuning_t *in) {
             return set_error(PERM_EINVAL, "layer_t[%d] = %d impossible", n, t);
         if (in->layer_xcd_remap[n] < -1 || in->layer_xcd_remap[n] > 4096)
             return set_error(PERM_EINVAL, "layer_xcd_remap[%d] = %d", n, in->layer_xcd_remap[n]);
-        if (in->layer_flags[n] & ~3)
+        if (in->layer_flags[n] & ~7)
             return set_error(PERM_EINVAL, "layer_flags[%d] = %d", n, in->layer_flags[n]);
         if (in->layer_thin[n] < -1 || in->layer_thin[n] > 65536)
             return set_error(PERM_EINVAL, "layer_thin[%d] = %d", n, in->layer_thin[n]);
@@ -1374,11 +1450,15 @@ int perm_profile_enable(int on) {
 int perm_profile_read(perm_profile_t *out) {
     if (!out) return set_error(PERM_EINVAL, "null pointer");
     std::vector<ProfEv> evs;
+    int64_t plain = 0;
     {
         std::lock_guard<std::mutex> lk(g_prof_mu);
         evs.swap(g_prof_events);
+        plain = g_prof_plain_layers;
+        g_prof_plain_layers = 0;
     }
     std::memset(out, 0, sizeof *out);
+    out->int_plain_layers = plain;
     int rc = PERM_OK;
     for (auto &e : evs) {
         float ms = 0.f;
@@ -1400,6 +1480,9 @@ int perm_profile_read(perm_profile_t *out) {
         } else if (e.kind == 4) {
             out->multi_c128_ms += ms;
             out->multi_c128_launches++;
+        } else if (e.kind == 6) {
+            out->block_c128_ms += ms;
+            out->block_c128_launches++;
         } else {
             out->multi_modp_ms += ms;
             out->multi_modp_launches++;

@@ -29,7 +29,7 @@ int tuned_batch_group(int n, size_t lds_bytes, int elem_bytes, int block);
 
 // Complex solve of a device matrix into a device result, stream-ordered.
 int solve_c128_device(int n, const void *a_dev, int64_t lda, void *result_dev, void *ws,
-                      size_t ws_bytes, hipStream_t s);
+                      size_t ws_bytes, hipStream_t s, bool allow_profile = true);
 
 // Workspace bytes of the complex path (both solve entry points).
 size_t c128_workspace_bytes(int n);
@@ -48,6 +48,9 @@ bool profiling_on();
 // kind 0 c128 layer, 1 modp layer, 2 batch, 3 Ryser, 4 repeated-column c128 layer, 5 its modp layer
 void profile_record(int kind, hipEvent_t start, hipEvent_t stop);
 hipEvent_t profile_event();
+// Adds to the count of plain 64-bit integer layers run (reported by
+// perm_profile_read).
+void profile_count_plain(int layers);
 
 // Monotonic clock in seconds.
 double now_seconds();

@@ -800,6 +800,104 @@ int perm_solve_multi(perm_dtype_t dt, int n, int m, const int32_t *mult, const v
     return PERM_OK;
 }
 
+// Repeated rows and columns: per(A) = per(A^T) (property 1 of section 3.1),
+// so one side is expanded and the other compressed into count vectors.  The
+// side compressed is the one with fewer count vectors, prod(mult + 1) (exact
+// 128-bit products: at most 2^64 each); ties compress the columns.
+extern "C++" {
+namespace {
+
+struct Bunched {
+    bool rows;                  // compress the rows (expand the columns of A^T)
+    int n, m;                   // expanded rows, compressed columns
+    const int32_t *mult;        // multiplicities of the compressed side
+};
+
+int bunched_shape(int r, const int32_t *row_mult, int c, const int32_t *col_mult, Bunched *b) {
+    if (r < 0 || c < 0 || (r > 0 && !row_mult) || (c > 0 && !col_mult))
+        return set_error(PERM_EINVAL, "bad multiplicity arrays");
+    int64_t nr = 0, nc = 0;
+    unsigned __int128 pr = 1, pc = 1;
+    for (int i = 0; i < r; i++) {
+        if (row_mult[i] < 1) return set_error(PERM_EINVAL, "row_mult[%d] = %d < 1", i, row_mult[i]);
+        nr += row_mult[i];
+        if (nr > PERM_MULTI_N_MAX) return set_error(PERM_ERANGE, "n > %d", PERM_MULTI_N_MAX);
+        pr *= (unsigned)(row_mult[i] + 1);
+    }
+    for (int j = 0; j < c; j++) {
+        if (col_mult[j] < 1) return set_error(PERM_EINVAL, "col_mult[%d] = %d < 1", j, col_mult[j]);
+        nc += col_mult[j];
+        if (nc > PERM_MULTI_N_MAX) return set_error(PERM_ERANGE, "n > %d", PERM_MULTI_N_MAX);
+        pc *= (unsigned)(col_mult[j] + 1);
+    }
+    if (nr != nc)
+        return set_error(PERM_EINVAL, "row multiplicities sum to %lld, column multiplicities to %lld", (long long)nr,
+                         (long long)nc);
+    b->rows = pr < pc;
+    b->n = (int)nr;
+    b->m = b->rows ? r : c;
+    b->mult = b->rows ? row_mult : col_mult;
+    return PERM_OK;
+}
+
+// The expanded n x m matrix (row-major, lda = m) of one orientation.
+template <typename T>
+std::vector<T> bunched_expand(const Bunched &b, int r, const int32_t *row_mult, int c, const int32_t *col_mult,
+                              const T *a, int64_t lda) {
+    std::vector<T> e((size_t)b.n * b.m);
+    size_t i2 = 0;
+    if (!b.rows) {  // rows of A repeated, columns compressed
+        for (int i = 0; i < r; i++)
+            for (int u = 0; u < row_mult[i]; u++, i2++)
+                for (int j = 0; j < c; j++) e[i2 * b.m + j] = a[(int64_t)i * lda + j];
+    } else {  // columns of A become repeated rows of A^T, rows compressed
+        for (int j = 0; j < c; j++)
+            for (int u = 0; u < col_mult[j]; u++, i2++)
+                for (int i = 0; i < r; i++) e[i2 * b.m + i] = a[(int64_t)i * lda + j];
+    }
+    return e;
+}
+
+}  // namespace
+}  // extern "C++"
+
+size_t perm_bunched_workspace_bytes(perm_dtype_t dt, int r, const int32_t *row_mult, int c, const int32_t *col_mult) {
+    Bunched b;
+    if (bunched_shape(r, row_mult, c, col_mult, &b) != PERM_OK) return 0;
+    return perm_multi_workspace_bytes(dt, b.n, b.m, b.mult);
+}
+
+int perm_bunched_orientation(int r, const int32_t *row_mult, int c, const int32_t *col_mult, int *rows) {
+    if (!rows) return set_error(PERM_EINVAL, "null pointer");
+    Bunched b;
+    const int rc = bunched_shape(r, row_mult, c, col_mult, &b);
+    if (rc) return rc;
+    *rows = b.rows ? 1 : 0;
+    return PERM_OK;
+}
+
+int perm_solve_bunched(perm_dtype_t dt, int r, const int32_t *row_mult, int c, const int32_t *col_mult, const void *a,
+                       int64_t lda, void *result, void *workspace, size_t ws_bytes, void *stream) {
+    try {
+        if (dt != PERM_INT64 && dt != PERM_COMPLEX128) return set_error(PERM_EINVAL, "bad dtype");
+        if (!result || (r > 0 && c > 0 && !a)) return set_error(PERM_EINVAL, "null pointer");
+        if (r > 0 && lda < c) return set_error(PERM_EINVAL, "lda = %lld < c = %d", (long long)lda, c);
+        Bunched b;
+        const int rc = bunched_shape(r, row_mult, c, col_mult, &b);
+        if (rc) return rc;
+        if (dt == PERM_INT64) {
+            const auto e = bunched_expand(b, r, row_mult, c, col_mult, (const int64_t *)a, lda);
+            return perm_solve_multi(dt, b.n, b.m, b.mult, e.data(), b.m > 0 ? b.m : 1, result, workspace, ws_bytes,
+                                    stream);
+        }
+        const auto e = bunched_expand(b, r, row_mult, c, col_mult, (const perm_c128_t *)a, lda);
+        return perm_solve_multi(dt, b.n, b.m, b.mult, e.data(), b.m > 0 ? b.m : 1, result, workspace, ws_bytes,
+                                stream);
+    } catch (const std::exception &ex) {
+        return set_error(PERM_EDEVICE, "internal error: %s", ex.what());
+    }
+}
+
 int perm_solve_multi_async(int n, int m, const int32_t *mult, const perm_c128_t *a_dev, int64_t lda,
                            perm_c128_t *result_dev, void *workspace, size_t ws_bytes, void *stream) {
     if (!result_dev) return set_error(PERM_EINVAL, "null result");
@@ -836,6 +934,39 @@ int perm_probe_fp64(double *tflops, void *stream) {
     (void)hipFree(d_out);
     if (e != hipSuccess) return hip_error(e, "FP64 probe");
     *tflops = 5.0 * probe_fma_flops(blocks, iters) / (ms * 1e-3) / 1e12;
+    return PERM_OK;
+}
+
+int perm_probe_int(double *mac_fold_gops, double *add64_gops, void *stream) {
+    if (!mac_fold_gops || !add64_gops) return set_error(PERM_EINVAL, "null pointer");
+    hipStream_t s = (hipStream_t)stream;
+    int dev = 0, cus = 0;
+    MHIP(hipGetDevice(&dev), "hipGetDevice");
+    MHIP(hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev), "hipDeviceGetAttribute");
+    const int blocks = std::max(1, cus) * 16;
+    uint64_t *d_out = nullptr;
+    MHIP(hipMalloc(&d_out, (size_t)blocks * sizeof(uint64_t)), "hipMalloc (probe)");
+    hipEvent_t e0 = nullptr, e1 = nullptr;
+    hipError_t e = hipEventCreate(&e0);
+    if (e == hipSuccess) e = hipEventCreate(&e1);
+    double rate[2] = {0.0, 0.0};
+    for (int mode = 0; mode < 2 && e == hipSuccess; mode++) {
+        const int iters = mode == 0 ? (1 << 8) : (1 << 11);  // a few ms per launch
+        float ms = 0.f;
+        e = launch_probe_int(d_out, blocks, iters, mode, s);  // warm-up
+        if (e == hipSuccess) e = hipEventRecord(e0, s);
+        for (int r = 0; r < 5 && e == hipSuccess; r++) e = launch_probe_int(d_out, blocks, iters, mode, s);
+        if (e == hipSuccess) e = hipEventRecord(e1, s);
+        if (e == hipSuccess) e = hipEventSynchronize(e1);
+        if (e == hipSuccess) e = hipEventElapsedTime(&ms, e0, e1);
+        if (e == hipSuccess) rate[mode] = 5.0 * probe_int_terms(blocks, iters) / (ms * 1e-3) / 1e9;
+    }
+    if (e0) (void)hipEventDestroy(e0);
+    if (e1) (void)hipEventDestroy(e1);
+    (void)hipFree(d_out);
+    if (e != hipSuccess) return hip_error(e, "integer probe");
+    *mac_fold_gops = rate[0];
+    *add64_gops = rate[1];
     return PERM_OK;
 }
 

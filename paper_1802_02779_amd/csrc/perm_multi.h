@@ -64,5 +64,10 @@ hipError_t launch_multi_layer_modp(const uint64_t *prev, uint64_t *next, size_t 
 // chains, `iters` steps each; probe_fma_flops gives the flops of one launch.
 hipError_t launch_probe_fma(double *out, int blocks, int iters, hipStream_t s);
 double probe_fma_flops(int blocks, int iters);
+// Integer probe (perm_probe.hip): mode 0 = 128-bit sums of 64 x 64-bit
+// products folded mod 2^61 - 1 every 16 terms, mode 1 = 64-bit additions;
+// probe_int_terms gives the terms of one launch.
+hipError_t launch_probe_int(uint64_t *out, int blocks, int iters, int mode, hipStream_t s);
+double probe_int_terms(int blocks, int iters);
 
 }  // namespace permgpu

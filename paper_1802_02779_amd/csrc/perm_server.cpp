@@ -137,10 +137,11 @@ void finish(perm_server_t *s, Running &r, int status) {
     r.busy = false;
 }
 
-// Launch one batch of small requests on slot i (called with the lock held;
-// only the scheduler thread calls it).
-int launch_small(perm_server_t *s, int i, std::vector<Request *> &reqs) {
-    Running &run = s->small_run[i];
+// Device work of a small batch on slot i (no lock held: only the scheduler
+// thread touches slots, the arena and running requests).  The carve-out at
+// `off` was reserved under the lock.
+int issue_small(perm_server_t *s, int i, const std::vector<Request *> &reqs, size_t off, size_t ws, size_t mats_b,
+                size_t res_b) {
     const int count = (int)reqs.size();
     std::vector<int32_t> ns(count);
     std::vector<int64_t> offs(count);
@@ -150,11 +151,6 @@ int launch_small(perm_server_t *s, int i, std::vector<Request *> &reqs) {
         offs[j] = elems;
         elems += (int64_t)reqs[j]->n * reqs[j]->n;
     }
-    const size_t ws = perm_batch_workspace_bytes(PERM_COMPLEX128, count, ns.data());
-    const size_t mats_b = ((size_t)std::max<int64_t>(elems, 1) * 16 + 255) & ~(size_t)255;
-    const size_t res_b = ((size_t)count * 16 + 255) & ~(size_t)255;
-    size_t off;
-    if (!s->arena.alloc(ws + mats_b + res_b, &off)) return PERM_EAGAIN;
     char *base = (char *)s->cfg.pool + off;
     perm_c128_t *pin_in = s->pin_small_in[i];
     for (int j = 0; j < count; j++)
@@ -171,26 +167,29 @@ int launch_small(perm_server_t *s, int i, std::vector<Request *> &reqs) {
     if (rc == PERM_OK &&
         hipMemcpyAsync(s->pin_small_out[i], base + mats_b, (size_t)count * 16, hipMemcpyDeviceToHost, st) != hipSuccess)
         rc = PERM_EDEVICE;
-    if (rc == PERM_OK && hipEventRecord(run.done, st) != hipSuccess) rc = PERM_EDEVICE;
-    run.reqs = reqs;
-    run.off = off;
-    run.bytes = ws + mats_b + res_b;
-    run.host_out = s->pin_small_out[i];
-    run.busy = true;
-    if (rc != PERM_OK) {
-        (void)hipStreamSynchronize(st);
-        finish(s, run, rc < 0 ? rc : PERM_EDEVICE);
-    }
-    return PERM_OK;
+    if (rc == PERM_OK && hipEventRecord(s->small_run[i].done, st) != hipSuccess) rc = PERM_EDEVICE;
+    if (rc != PERM_OK) (void)hipStreamSynchronize(st);
+    return rc;
 }
 
-int launch_large(perm_server_t *s, int i, Request *q) {
-    Running &run = s->large_run[i];
+// Bytes a small batch needs from the pool: workspace, matrices, results.
+void small_bytes(const std::vector<Request *> &reqs, size_t *ws, size_t *mats_b, size_t *res_b) {
+    std::vector<int32_t> ns;
+    int64_t elems = 0;
+    for (auto *q : reqs) {
+        ns.push_back(q->n);
+        elems += (int64_t)q->n * q->n;
+    }
+    *ws = perm_batch_workspace_bytes(PERM_COMPLEX128, (int)ns.size(), ns.data());
+    *mats_b = ((size_t)std::max<int64_t>(elems, 1) * 16 + 255) & ~(size_t)255;
+    *res_b = ((size_t)reqs.size() * 16 + 255) & ~(size_t)255;
+}
+
+// Device work of one large request on slot i (no lock held).
+int issue_large(perm_server_t *s, int i, Request *q, size_t off) {
     const int n = q->n;
     const size_t ws = c128_workspace_bytes(n);
     const size_t mat_b = ((size_t)n * n * 16 + 255) & ~(size_t)255;
-    size_t off;
-    if (!s->arena.alloc(ws + mat_b + 256, &off)) return PERM_EAGAIN;
     char *base = (char *)s->cfg.pool + off;
     char *d_a = base + ws, *d_res = base + ws + mat_b;
     hipStream_t st = s->large_stream[i];
@@ -202,22 +201,29 @@ int launch_large(perm_server_t *s, int i, Request *q) {
     if (rc == PERM_OK) rc = solve_c128_device(n, d_a, n > 0 ? n : 1, d_res, base, ws, st);
     if (rc == PERM_OK && hipMemcpyAsync(s->pin_large_out[i], d_res, 16, hipMemcpyDeviceToHost, st) != hipSuccess)
         rc = PERM_EDEVICE;
-    if (rc == PERM_OK && hipEventRecord(run.done, st) != hipSuccess) rc = PERM_EDEVICE;
-    run.reqs.assign(1, q);
-    run.off = off;
-    run.bytes = ws + mat_b + 256;
-    run.host_out = s->pin_large_out[i];
-    run.busy = true;
-    if (rc != PERM_OK) {
-        (void)hipStreamSynchronize(st);
-        finish(s, run, rc < 0 ? rc : PERM_EDEVICE);
-    }
-    return PERM_OK;
+    if (rc == PERM_OK && hipEventRecord(s->large_run[i].done, st) != hipSuccess) rc = PERM_EDEVICE;
+    if (rc != PERM_OK) (void)hipStreamSynchronize(st);
+    return rc;
 }
 
+size_t large_bytes(int n) { return c128_workspace_bytes(n) + (((size_t)n * n * 16 + 255) & ~(size_t)255) + 256; }
+
+// One launch decided under the lock and issued after it is released.
+struct Planned {
+    bool small;
+    int slot;
+    std::vector<Request *> reqs;
+    size_t off, ws, mats_b, res_b;
+};
+
+// The scheduler holds the mutex only to look at completions, admit
+// requests (budget, carve-out, slot) and record outcomes; copies into
+// pinned memory and every launch happen with the mutex released, so
+// submit and poll never wait behind host-side launch work.
 void scheduler(perm_server_t *s) {
     (void)hipSetDevice(s->device);
     std::unique_lock<std::mutex> lk(s->mu);
+    std::vector<Planned> plan;
     for (;;) {
         bool progress = false;
         // completions
@@ -240,15 +246,25 @@ void scheduler(perm_server_t *s) {
             for (auto &r : s->large_run) busy |= r.busy;
             if (!busy) break;
         } else {
+            plan.clear();
             // large requests: strict FIFO, one per free slot while memory allows
             for (size_t i = 0; i < s->large_run.size() && !s->large_q.empty(); i++) {
                 if (s->large_run[i].busy) continue;
                 Request *q = s->large_q.front();
                 if (s->in_use + q->charge > s->budget) break;
-                if (launch_large(s, (int)i, q) != PERM_OK) break;  // pool fragmented: wait
+                size_t off;
+                const size_t bytes = large_bytes(q->n);
+                if (!s->arena.alloc(bytes, &off)) break;  // pool fragmented: wait
+                Running &run = s->large_run[i];
+                run.reqs.assign(1, q);
+                run.off = off;
+                run.bytes = bytes;
+                run.host_out = s->pin_large_out[i];
+                run.busy = true;
                 s->in_use += q->charge;
                 s->large_q.pop_front();
                 s->queued--;
+                plan.push_back({false, (int)i, {q}, off, 0, 0, 0});
                 progress = true;
             }
             // small requests: everything waiting (up to the batch limit) that fits
@@ -264,13 +280,35 @@ void scheduler(perm_server_t *s) {
                     s->small_q.pop_front();
                 }
                 if (take.empty()) break;
-                if (launch_small(s, i, take) != PERM_OK) {
+                size_t ws, mats_b, res_b, off;
+                small_bytes(take, &ws, &mats_b, &res_b);
+                if (!s->arena.alloc(ws + mats_b + res_b, &off)) {
                     for (auto it = take.rbegin(); it != take.rend(); ++it) s->small_q.push_front(*it);
                     break;
                 }
+                Running &run = s->small_run[i];
+                run.reqs = take;
+                run.off = off;
+                run.bytes = ws + mats_b + res_b;
+                run.host_out = s->pin_small_out[i];
+                run.busy = true;
                 s->in_use += charge;
                 s->queued -= take.size();
+                plan.push_back({true, i, take, off, ws, mats_b, res_b});
                 progress = true;
+            }
+            if (!plan.empty()) {
+                lk.unlock();
+                std::vector<int> rcs;
+                for (auto &pl : plan)
+                    rcs.push_back(pl.small ? issue_small(s, pl.slot, pl.reqs, pl.off, pl.ws, pl.mats_b, pl.res_b)
+                                           : issue_large(s, pl.slot, pl.reqs[0], pl.off));
+                lk.lock();
+                for (size_t k = 0; k < plan.size(); k++) {
+                    if (rcs[k] == PERM_OK) continue;
+                    Running &run = plan[k].small ? s->small_run[plan[k].slot] : s->large_run[plan[k].slot];
+                    finish(s, run, rcs[k] < 0 ? rcs[k] : PERM_EDEVICE);
+                }
             }
         }
         if (!progress) s->cv.wait_for(lk, std::chrono::microseconds(20));

@@ -52,6 +52,7 @@ EXPORTS = [
     "perm_tuning_set", "perm_tuning_load", "perm_tuning_save", "perm_tuning_key",
     "perm_profile_enable", "perm_profile_read", "perm_multi_workspace_bytes", "perm_solve_multi",
     "perm_solve_multi_async", "perm_multi_plan_info", "perm_probe_fp64",
+    "perm_probe_int", "perm_bunched_workspace_bytes", "perm_bunched_orientation", "perm_solve_bunched",
 ]
 
 
@@ -109,7 +110,9 @@ class perm_profile_t(ctypes.Structure):
                 ("batch_ms", ctypes.c_double), ("batch_launches", ctypes.c_int64),
                 ("ryser_ms", ctypes.c_double), ("ryser_launches", ctypes.c_int64),
                 ("multi_c128_ms", ctypes.c_double), ("multi_c128_launches", ctypes.c_int64),
-                ("multi_modp_ms", ctypes.c_double), ("multi_modp_launches", ctypes.c_int64)]
+                ("multi_modp_ms", ctypes.c_double), ("multi_modp_launches", ctypes.c_int64),
+                ("block_c128_ms", ctypes.c_double), ("block_c128_launches", ctypes.c_int64),
+                ("int_plain_layers", ctypes.c_int64)]
 
 
 _lock = threading.Lock()
@@ -138,6 +141,14 @@ def lib() -> ctypes.CDLL:
         L.perm_solve.restype = i32
         L.perm_solve_async.argtypes = [i32, vp, i64, vp, vp, sz, vp]
         L.perm_solve_async.restype = i32
+        L.perm_bunched_workspace_bytes.argtypes = [i32, i32, vp, i32, vp]
+        L.perm_bunched_workspace_bytes.restype = sz
+        L.perm_bunched_orientation.argtypes = [i32, vp, i32, vp, ctypes.POINTER(ctypes.c_int)]
+        L.perm_bunched_orientation.restype = i32
+        L.perm_solve_bunched.argtypes = [i32, i32, vp, i32, vp, vp, i64, vp, vp, sz, vp]
+        L.perm_solve_bunched.restype = i32
+        L.perm_probe_int.argtypes = [ctypes.POINTER(ctypes.c_double), ctypes.POINTER(ctypes.c_double), vp]
+        L.perm_probe_int.restype = i32
         L.perm_ryser_workspace_bytes.argtypes = [i32, i32]
         L.perm_ryser_workspace_bytes.restype = sz
         L.perm_ryser.argtypes = [i32, i32, vp, i64, vp, vp, sz, vp]
@@ -354,35 +365,50 @@ def perm_solve_multi_async(n: int, mult, a_dev, lda: int, result_dev, workspace,
                                         _stream_ptr(stream)))
 
 
+def _mults(row_mult, col_mult):
+    rm = np.ascontiguousarray(np.asarray(row_mult, dtype=np.int32))
+    cm = np.ascontiguousarray(np.asarray(col_mult, dtype=np.int32))
+    if rm.ndim != 1 or cm.ndim != 1:
+        raise ValueError("multiplicities are 1-D")
+    return rm, cm
+
+
 def bunched_orientation(row_mult, col_mult) -> bool:
     """True when perm_solve_bunched compresses the rows (runs on the
-    transpose): the side with fewer count vectors, prod(mult + 1), is the one
-    compressed; ties keep the columns."""
-    r = np.asarray(row_mult, dtype=np.float64)
-    c = np.asarray(col_mult, dtype=np.float64)
-    return float(np.sum(np.log2(r + 1.0))) < float(np.sum(np.log2(c + 1.0))) - 1e-9
+    transpose): the library's rule, the side with fewer count vectors
+    prod(mult + 1); ties keep the columns."""
+    rm, cm = _mults(row_mult, col_mult)
+    rows = ctypes.c_int()
+    _check(lib().perm_bunched_orientation(rm.shape[0], rm.ctypes.data, cm.shape[0], cm.ctypes.data,
+                                          ctypes.byref(rows)))
+    return bool(rows.value)
+
+
+def perm_bunched_workspace_bytes(dtype: int, row_mult, col_mult) -> int:
+    rm, cm = _mults(row_mult, col_mult)
+    return int(lib().perm_bunched_workspace_bytes(dtype, rm.shape[0], rm.ctypes.data, cm.shape[0], cm.ctypes.data))
 
 
 def perm_solve_bunched(A, row_mult, col_mult, workspace=None, stream=None):
     """Permanent of the n x n matrix with row i of the r x c matrix A repeated
     row_mult[i] times and column j repeated col_mult[j] times (sum row_mult =
-    sum col_mult = n): the amplitude, up to the factor
-    1 / sqrt(prod row_mult! prod col_mult!), of bosons that enter r modes and
-    leave c modes with those occupations.  per(A) = per(A^T), so one side is
-    expanded and the other is compressed into count vectors
-    (perm_solve_multi); the side compressed is the one with fewer count
-    vectors (bunched_orientation), which also fixes the fp64 chain, so the
-    complex result is a deterministic function of the inputs."""
+    sum col_mult = n); see perm_solve_bunched in include/perm.h."""
+    rm, cm = _mults(row_mult, col_mult)
     A = np.asarray(A)
-    rm = np.asarray(row_mult, dtype=np.int64)
-    cm = np.asarray(col_mult, dtype=np.int64)
     if A.ndim != 2 or A.shape != (rm.shape[0], cm.shape[0]):
         raise ValueError("one multiplicity per row and per column of A")
-    if int(rm.sum()) != int(cm.sum()):
-        raise ValueError("row and column multiplicities must have the same sum")
-    if bunched_orientation(rm, cm):
-        return perm_solve_multi(np.repeat(A.T, cm, axis=0), rm, workspace=workspace, stream=stream)
-    return perm_solve_multi(np.repeat(A, rm, axis=0), cm, workspace=workspace, stream=stream)
+    dt = _dtype_of(A)
+    A = np.ascontiguousarray(A, dtype=np.complex128 if dt == PERM_COMPLEX128 else np.int64)
+    if workspace is None:
+        need = perm_bunched_workspace_bytes(dt, rm, cm)
+        workspace = device_buffer(need) if need else None
+    ws_ptr = workspace.data_ptr() if workspace is not None else None
+    ws_bytes = workspace.numel() * workspace.element_size() if workspace is not None else 0
+    r, c = A.shape
+    out = perm_int_t() if dt == PERM_INT64 else perm_c128_t()
+    _check(lib().perm_solve_bunched(dt, r, rm.ctypes.data, c, cm.ctypes.data, A.ctypes.data if A.size else None,
+                                    max(c, 1), ctypes.byref(out), ws_ptr, ws_bytes, _stream_ptr(stream)))
+    return out.value() if dt == PERM_INT64 else complex(out.re, out.im)
 
 
 def perm_multi_plan_info(mult, check: bool = False) -> perm_multi_plan_info_t:
@@ -399,6 +425,14 @@ def perm_probe_fp64(stream=None) -> float:
     v = ctypes.c_double()
     _check(lib().perm_probe_fp64(ctypes.byref(v), _stream_ptr(stream)))
     return float(v.value)
+
+
+def perm_probe_int(stream=None):
+    """(mac_fold, add64) rates of the integer sweep's per-term arithmetic, in
+    1e9 terms per second (measurement probe)."""
+    a, b = ctypes.c_double(), ctypes.c_double()
+    _check(lib().perm_probe_int(ctypes.byref(a), ctypes.byref(b), _stream_ptr(stream)))
+    return float(a.value), float(b.value)
 
 
 def perm_batch_workspace_bytes(dtype: int, ns: np.ndarray) -> int:

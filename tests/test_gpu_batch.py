@@ -149,3 +149,42 @@ def test_batch_full_size_sampled(P):
     assert (c_bits_arr(results.cpu().numpy()) == c_bits_arr(got)).all()
     del d_mats, results, ws
     torch.cuda.empty_cache()
+
+
+def test_batch_full_size_every_output_digest(P):
+    """Every one of the 2^20 outputs of the timed workload against the
+    oracle: results start as NaN (a skipped matrix would stay NaN), the
+    graph launch fills them, and the SHA-256 of all results (little-endian
+    complex128, batch order) must equal the digest the oracle's results gave
+    (tests/golden/make_large_configs.py); per-order digests name the order
+    on a mismatch.  A replay after eager work gives the same digest."""
+    import hashlib
+    import json
+    import os
+    import torch
+    with open(os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden", "large_configs.json")) as f:
+        g = json.load(f)["batch_2p20_s2018_s1"]
+    count = 1 << 20
+    U = inputs.haar_unitary(64, seed=2018)
+    b = inputs.submatrix_batch(U, count, 3, 12, seed=1)
+    assert g["count"] == count
+    results = torch.full((count,), float("nan"), dtype=torch.complex128, device="cuda")
+    print("[gpu] batch 2^20 digest", flush=True)
+    got, d_mats, results, ws = run_batch(P, b, flags=P.PERM_BATCH_GRAPH, results=results)
+
+    def check(arr):
+        assert not np.isnan(arr.view(np.float64)).any()
+        if hashlib.sha256(np.ascontiguousarray(arr).astype("<c16").tobytes()).hexdigest() != g["sha256"]:
+            bad = [n for n in range(3, 13)
+                   if hashlib.sha256(np.ascontiguousarray(arr[b.ns == n]).astype("<c16").tobytes()).hexdigest()
+                   != g["sha256_by_order"][str(n)]]
+            raise AssertionError(f"batch results differ from the oracle's for orders {bad}")
+
+    check(got)
+    results.fill_(float("nan"))
+    torch.cuda.synchronize()
+    P.perm_solve_batch(P.PERM_COMPLEX128, b.ns, b.offsets, d_mats, results, ws,
+                       flags=P.PERM_BATCH_GRAPH | P.PERM_BATCH_REUSE | P.PERM_BATCH_SYNC)
+    check(results.cpu().numpy())
+    del d_mats, results, ws
+    torch.cuda.empty_cache()

@@ -1,10 +1,13 @@
-"""Orders 31..34 (beyond the CPU oracle, whose 2^n tables would not fit the
-host): parity rests on closed forms and on two independent GPU algorithms
-agreeing -- the Store-zechin layer sweep and Ryser's eq. (4) -- bit for bit
-for integers, and within the measured 1e-6 gate (as at n = 26, 28) for
-complex Gaussian inputs.  Workspaces here reach 112 GB; the cache is
-emptied after each test."""
+"""Orders 31..34, beyond the oracle's 2^n tables: integer 0/1 results are
+exact against values the oracle computed by eq. (4) mod p in O(n) memory
+(stored in tests/golden/large_configs.json) and against closed forms at
+every order; two independent GPU algorithms -- the Store-zechin layer sweep
+and Ryser's eq. (4) -- agree bit for bit for integers, and within the
+measured 1e-6 gate (as at n = 26, 28) for complex Gaussian inputs.
+Workspaces here reach 112 GB; the cache is emptied after each test."""
+import json
 import math
+import os
 
 import numpy as np
 import pytest
@@ -56,7 +59,21 @@ def test_int_bernoulli_sweep_equals_ryser(P, n):
     assert sz > 0
 
 
-@pytest.mark.parametrize("n", [32, 34])
+@pytest.fixture(scope="module")
+def golden():
+    with open(os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden", "large_configs.json")) as f:
+        return json.load(f)
+
+
+@pytest.mark.parametrize("n", [31, 32, 33, 34])
+def test_int_bernoulli_vs_stored_oracle(P, golden, n):
+    """Bernoulli(1/2) 0/1 matrices (seed 0): exact against the oracle's
+    eq. (4) mod p values."""
+    print(f"[gpu] int 0/1 n={n} vs stored oracle value", flush=True)
+    assert P.perm_solve(inputs.bernoulli01(n, seed=0)) == int(golden[f"int_n{n}_bern_s0"]["value"])
+
+
+@pytest.mark.parametrize("n", [31, 32, 33, 34])
 def test_int_closed_forms(P, n):
     J = np.ones((n, n), dtype=np.int64)
     I = np.eye(n, dtype=np.int64)

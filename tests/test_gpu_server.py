@@ -122,3 +122,46 @@ def test_destroy_with_pending_requests(P):
     t0 = time.time()
     P.perm_server_destroy(srv)
     assert time.time() - t0 < 30
+
+
+def test_large_orders_overlap_and_match_stored_values(P):
+    """Six large requests (n = 25..28) admitted together into a 16 GiB pool
+    (carve-outs reach past 4 GiB), mixed with small ones: each result is
+    bitwise the stored oracle value (or, for the seeds without one, the same
+    matrix solved alone), and requests really are in flight together."""
+    import json
+    import os
+    with open(os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden", "large_configs.json")) as f:
+        golden = json.load(f)
+    reqs = [(28, 0), (28, 1), (28, 2), (27, 0), (26, 1), (25, 0)]
+    mats = [inputs.complex_gaussian(n, seed=s) for n, s in reqs]
+    refs = []
+    for (n, s), A in zip(reqs, mats):
+        g = golden.get(f"c128_n{n}_s{s}")
+        refs.append((int(g["re_bits"], 16), int(g["im_bits"], 16)) if g else bits(P.perm_solve(A)))
+    U = inputs.haar_unitary(64, seed=41)
+    rng = np.random.default_rng(41)
+    small = []
+    for n in rng.integers(5, 13, size=24):
+        r, c = rng.permutation(64)[:n], rng.permutation(64)[:n]
+        small.append(np.ascontiguousarray(U[np.ix_(r, c)]))
+    pool = P.device_buffer(16 << 30)
+    srv = P.perm_server_create(pool, max_large_slots=6, queue_capacity=100, small_n_max=12, max_small_batch=8)
+    try:
+        print("[gpu] server: 6 large (n=25..28) + 24 small", flush=True)
+        tl = [P.perm_server_submit(srv, A) for A in mats]
+        ts = [P.perm_server_submit(srv, A) for A in small]
+        res = wait_all(P, srv, tl + ts, timeout=120.0)
+    finally:
+        P.perm_server_destroy(srv)
+        del pool
+    for t, (n, s), ref in zip(tl, reqs, refs):
+        z, st = res[t]
+        assert st.status == 0 and st.n == n
+        assert bits(z) == ref, (n, s)
+    for t, A in zip(ts, small):
+        assert bits(res[t][0]) == bits(native.per_c128(A))
+    spans = [(res[t][1].t_start, res[t][1].t_done) for t in tl]
+    overlapping = sum(1 for i in range(len(spans)) for j in range(i + 1, len(spans))
+                      if spans[i][0] < spans[j][1] and spans[j][0] < spans[i][1])
+    assert overlapping >= 1, spans

@@ -51,7 +51,7 @@ def check_complex(P, A, label=""):
 
 
 # ----------------------------------------------------------- complex128
-@pytest.mark.parametrize("n", list(range(2, 19)) + [20, 22])
+@pytest.mark.parametrize("n", list(range(2, 23)))
 def test_complex_gaussian_bitwise(P, n):
     seeds = range(3) if n <= 16 else range(1)
     for s in seeds:
@@ -183,8 +183,12 @@ def test_determinism_and_tuning_variants(P):
 
 
 # --------------------------------------------------------- full sizes
-@pytest.mark.parametrize("key,n,seed", [("c128_n26_s0", 26, 0), ("c128_n26_s1", 26, 1),
-                                        ("c128_n28_s0", 28, 0)])
+FULL_COMPLEX = [("c128_n23_s0", 23, 0), ("c128_n24_s0", 24, 0), ("c128_n25_s0", 25, 0),
+                ("c128_n26_s0", 26, 0), ("c128_n26_s1", 26, 1), ("c128_n27_s0", 27, 0),
+                ("c128_n28_s0", 28, 0), ("c128_n29_s0", 29, 0), ("c128_n30_s0", 30, 0)]
+
+
+@pytest.mark.parametrize("key,n,seed", FULL_COMPLEX)
 def test_full_size_complex(P, golden, key, n, seed):
     g = golden[key]
     A = inputs.complex_gaussian(n, seed=seed)
@@ -216,10 +220,93 @@ def test_int_config_n10(P, golden):
         assert P.perm_solve(A) == int(golden[f"int_n10_u09_s{s}"]["value"])
 
 
-def test_int_full_size_bernoulli_n30(P, golden):
-    print("[gpu] int n=30 Bernoulli", flush=True)
-    A = inputs.bernoulli01(30, seed=0)
-    assert P.perm_solve(A) == int(golden["int_n30_bern_s0"]["value"])
+@pytest.mark.parametrize("n", [25, 27, 29, 30])
+def test_int_full_size_bernoulli(P, golden, n):
+    print(f"[gpu] int n={n} Bernoulli", flush=True)
+    A = inputs.bernoulli01(n, seed=0)
+    assert P.perm_solve(A) == int(golden[f"int_n{n}_bern_s0"]["value"])
+
+
+def test_complex_dyadic_n20_true_error(P):
+    """Dyadic complex Gaussian matrices of order 20 (parts multiples of
+    2^-30), whose exact permanents the oracle computes over the Gaussian
+    integers: the GPU result is bitwise the oracle's fp64 chain, lies within
+    the derived chain bound of the exact value, and over 16 seeds the median
+    relative error is at most 1e-12."""
+    from fractions import Fraction
+    import statistics
+    from test_oracle_native import chain_error_bound
+    rel = []
+    for seed in range(16):
+        A = inputs.dyadic_complex(20, seed=7000 + seed, bits=30)
+        print(f"[gpu] dyadic n=20 seed={seed}", flush=True)
+        z = P.perm_solve(A)
+        assert c_bits(z) == c_bits(native.per_c128(A)), seed
+        re, im = native.per_dyadic_exact(A, 30)
+        err = math.hypot(float(Fraction(z.real) - re), float(Fraction(z.imag) - im))
+        assert err <= chain_error_bound(20) * native.per_abs(A) * (1 + 1e-12), seed
+        rel.append(err / math.hypot(float(re), float(im)))
+    assert statistics.median(rel) <= 1e-12, rel
+
+
+def test_int_plain_prefix_row_sum_branch(P):
+    """Rows with two nonzero entries (a_ii = v_i, a_i,i+1 = 1, a_n-1,0 = 1):
+    per = prod v_i + 1, and the layer bound min(R_{k-1}, k M_{k-1}) takes
+    the row sum R = v + 1 in every row but the first.  With v_0 = 2^30,
+    v_1..v_4 = 2^10 and v_i = 1 after them the bound allows plain 64-bit
+    layers up to k = 4 (the stored value F({0..3}) is 2^60) and the largest
+    stored value of layer 5 is 2^70; the value needs two primes and the
+    redundant one, one sweep.  A row index off by one in the row-sum branch
+    would take rows 1..k (factors 2^10 and then 2) and run every layer in
+    plain arithmetic, which overflows."""
+    n = 24
+    v = [2 ** 30] + [2 ** 10] * 4 + [1] * (n - 5)
+    A = np.zeros((n, n), dtype=np.int64)
+    for i in range(n):
+        A[i, i] = v[i]
+        A[i, (i + 1) % n] = 1
+    want = math.prod(v) + 1
+    # plain layers by the rule, computed here: product of the per-row factors
+    B, K = 1, 0
+    for k in range(1, n + 1):
+        R, M = int(np.abs(A[k - 1]).sum()), int(np.abs(A[k - 1]).max())
+        B *= min(R, k * M)
+        if B > 2 ** 63 - 1:
+            break
+        K = k
+    assert K == 4
+    P.perm_profile_enable(True)
+    try:
+        P.perm_profile_read()
+        got = P.perm_solve(A)
+        prof = P.perm_profile_read()
+    finally:
+        P.perm_profile_enable(False)
+    assert got == want == native.per_int(A)
+    assert prof.int_plain_layers == K - 1  # layers 2..K
+
+
+def test_int_plain_layers_computed_once_for_many_primes(P):
+    """A 0/1 matrix of order 33 needs four primes, more than one sweep
+    carries: the plain layers (2..21 here) run once and serve every prime."""
+    n = 33
+    A = inputs.bernoulli01(n, seed=5)
+    P.perm_profile_enable(True)
+    try:
+        P.perm_profile_read()
+        got = P.perm_solve(A)
+        prof = P.perm_profile_read()
+    finally:
+        P.perm_profile_enable(False)
+    assert got == P.perm_ryser(A)
+    B, K = 1, 0
+    for k in range(1, n + 1):
+        row = np.abs(A[k - 1])
+        B *= min(int(row.sum()), k * int(row.max()))
+        if B > 2 ** 63 - 1:
+            break
+        K = k
+    assert prof.int_plain_layers == K - 1, (prof.int_plain_layers, K)
 
 
 def test_int_closed_forms_n30(P):
@@ -303,9 +390,9 @@ def test_full_sizes_under_shipped_tuning(P, golden):
     try:
         if P.perm_tuning_load(path) != 0:
             pytest.skip("the shipped tuning table is for another GPU key")
-        for key, n in (("c128_n26_s0", 26), ("c128_n28_s0", 28)):
+        for key, n, _ in FULL_COMPLEX:
             g = golden[key]
-            A = inputs.complex_gaussian(n, seed=0)
+            A = inputs.complex_gaussian(n, seed=int(key.rsplit("_s", 1)[1]))
             d_a = torch.from_numpy(A).cuda()
             d_r = torch.zeros(1, dtype=torch.complex128, device="cuda")
             ws = P.device_buffer(P.perm_workspace_bytes(P.PERM_COMPLEX128, n))
@@ -315,8 +402,34 @@ def test_full_sizes_under_shipped_tuning(P, golden):
             z = complex(d_r.cpu().numpy()[0])
             assert c_bits(z) == (int(g["re_bits"], 16), int(g["im_bits"], 16)), key
             del ws
-        print("[gpu] shipped tuning int n=30", flush=True)
-        assert P.perm_solve(inputs.bernoulli01(30, seed=0)) == int(golden["int_n30_bern_s0"]["value"])
+        for n in (25, 27, 29, 30):
+            print(f"[gpu] shipped tuning int n={n}", flush=True)
+            assert P.perm_solve(inputs.bernoulli01(n, seed=0)) == int(golden[f"int_n{n}_bern_s0"]["value"])
     finally:
         P.perm_tuning_set(saved)
         torch.cuda.empty_cache()
+
+
+@pytest.mark.parametrize("n", [24, 25, 26, 27, 28, 29, 30])
+def test_block_sweep_bitwise(P, golden, n):
+    """Bit 2 of layer_flags runs the block sweep (one workgroup per high
+    part, all low parts of all popcounts, one launch per high level): the
+    same stored values and chains, so the same bits as the oracle, for
+    several low-column counts and XCD run lengths."""
+    g = golden[f"c128_n{n}_s0"]
+    want = (int(g["re_bits"], 16), int(g["im_bits"], 16))
+    A = inputs.complex_gaussian(n, seed=0)
+    saved = P.perm_tuning_get()
+    try:
+        for t, remap in ((12, 64), (13, 8), (11, 0), (10, 3)):
+            if n - t > 22:
+                continue
+            tu = P.perm_tuning_t.from_buffer_copy(saved)
+            tu.layer_t[n] = t
+            tu.layer_xcd_remap[n] = remap
+            tu.layer_flags[n] = 4
+            P.perm_tuning_set(tu)
+            print(f"[gpu] block sweep n={n} t={t} remap={remap}", flush=True)
+            assert c_bits(P.perm_solve(A)) == want, (n, t, remap)
+    finally:
+        P.perm_tuning_set(saved)

@@ -142,7 +142,15 @@ def test_bunched_orientation_rule(perm):
     assert not perm.bunched_orientation([1, 1, 1, 1], [2, 2])   # columns compress better
     assert perm.bunched_orientation([3, 1], [1, 1, 1, 1])       # rows compress better
     assert not perm.bunched_orientation([2, 1], [2, 1])         # tie keeps the columns
+    # the rule compares prod(mult + 1) exactly: 4 * 2 * 2 = 16 against 3 * 3 * 2 = 18
+    assert perm.bunched_orientation([3, 1, 1], [2, 2, 1])
+    assert not perm.bunched_orientation([2, 2, 1], [3, 1, 1])
+    assert not perm.bunched_orientation([2, 2, 1], [1, 2, 2])  # tie
+    with pytest.raises(perm.PermError) as e:
+        perm.bunched_orientation([1, 1], [1, 2])  # sums differ
+    assert e.value.code == perm.PERM_EINVAL
+    with pytest.raises(perm.PermError):
+        perm.bunched_orientation([1, 0], [1])  # a multiplicity below 1
+    assert perm.perm_bunched_workspace_bytes(perm.PERM_COMPLEX128, [1, 1], [1, 2]) == 0
     with pytest.raises(ValueError):
-        perm.perm_solve_bunched(np.ones((2, 2)), [1, 1], [1, 2])
-    with pytest.raises(ValueError):
-        perm.perm_solve_bunched(np.ones((2, 3)), [1, 2], [1, 2])
+        perm.perm_solve_bunched(np.ones((2, 3), dtype=np.complex128), [1, 2], [1, 2])  # one mult per row and column
