@@ -122,6 +122,31 @@ int perm_solve(perm_dtype_t dt, int n, const void *a, int64_t lda, void *result,
 int perm_solve_async(int n, const perm_c128_t *a_dev, int64_t lda, perm_c128_t *result_dev,
                      void *workspace, size_t ws_bytes, void *stream);
 
+/* Allocation-free variant of perm_solve_async, for callers that cannot
+ * allocate device memory (code being captured into a HIP graph, serving
+ * loops, harnesses that forbid hipMalloc): the same kernels and the same
+ * result bits, but the layer tables and the packed matrix live in a fixed
+ * device array of PERM_NOALLOC_SCRATCH_BYTES bytes inside the library (one
+ * per device, held until the process ends) instead of a caller workspace.
+ * The call itself allocates nothing and frees nothing.
+ *   n          0 <= n <= PERM_NOALLOC_N_MAX (the largest order whose two
+ *              layer tables fit the array).
+ *   a_dev      device complex128 matrix, row-major, lda >= n.
+ *   result_dev device perm_c128_t output.
+ *   stream     the stream every kernel is ordered on.
+ * Stream-ordered; returns once the work is queued.  The first call on a
+ * device also builds the library's rank tables and synchronizes `stream`
+ * (make that call outside any graph capture).  Every call on one device
+ * shares its array, so calls that may overlap on that device (different
+ * streams, or threads) race and give undefined results: order them on one
+ * stream.  Nothing in the array has to start at zero (each layer is fully
+ * written before it is read).  Errors: PERM_EINVAL (null pointer, n < 0,
+ * lda < n), PERM_ERANGE (n > PERM_NOALLOC_N_MAX), PERM_EDEVICE. */
+#define PERM_NOALLOC_N_MAX 22
+#define PERM_NOALLOC_SCRATCH_BYTES ((size_t)24 << 20)
+int perm_solve_async_noalloc(int n, const perm_c128_t *a_dev, int64_t lda, perm_c128_t *result_dev,
+                             void *stream);
+
 /* ------------------------------------------------------------- batch --- */
 
 #define PERM_BATCH_SYNC 1u   /* wait for completion before returning */

@@ -9,3 +9,4 @@
 #include "perm_ryser.hip"
 #include "perm_multi.hip"
 #include "perm_probe.hip"
+#include "perm_noalloc.hip"

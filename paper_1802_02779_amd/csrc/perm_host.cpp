@@ -1211,6 +1211,29 @@ int perm_solve_async(int n, const perm_c128_t *a_dev, int64_t lda, perm_c128_t *
     }
 }
 
+int perm_solve_async_noalloc(int n, const perm_c128_t *a_dev, int64_t lda, perm_c128_t *result_dev,
+                             void *stream) {
+    try {
+        t_err.clear();
+        if (n < 0) return set_error(PERM_EINVAL, "n = %d < 0", n);
+        if (n > PERM_NOALLOC_N_MAX)
+            return set_error(PERM_ERANGE, "n = %d > %d: the allocation-free solve keeps its tables in a fixed "
+                             "%zu-byte device array", n, PERM_NOALLOC_N_MAX, (size_t)PERM_NOALLOC_SCRATCH_BYTES);
+        if (!result_dev || (n > 0 && !a_dev)) return set_error(PERM_EINVAL, "null pointer");
+        if (n > 0 && lda < n) return set_error(PERM_EINVAL, "lda = %lld < n = %d", (long long)lda, n);
+        void *ws = nullptr;
+        size_t ws_bytes = 0;
+        HIPCALL(noalloc_scratch(&ws, &ws_bytes), "hipGetSymbolAddress(scratch)");
+        if (c128_workspace_bytes(n) > ws_bytes)
+            return set_error(PERM_EDEVICE, "internal error: order %d needs %zu scratch bytes, the array holds %zu", n,
+                             c128_workspace_bytes(n), ws_bytes);
+        // profiling events are not created here: hipEventCreate allocates
+        return solve_c128_device(n, a_dev, lda, result_dev, ws, ws_bytes, (hipStream_t)stream, false);
+    } catch (...) {
+        return set_error(PERM_EDEVICE, "internal error");
+    }
+}
+
 size_t perm_ryser_workspace_bytes(perm_dtype_t dt, int n) {
     if (n < 0 || n > PERM_N_MAX) return 0;
     if (dt == PERM_COMPLEX128) return ryser_c128_workspace_bytes(n);

@@ -157,6 +157,11 @@ size_t block_lds_bytes_c128(const BlockArgs &a);
 hipError_t launch_block_c128(const void *prev, void *cur, const void *packed, const BlockArgs &a, hipStream_t s);
 hipError_t launch_block_readout_c128(const void *last, int t, void *result, hipStream_t s);
 
+// ---- allocation-free solve (perm_noalloc.hip) ----
+// Device address and size of the file-scope scratch array on the current
+// device (looked up once per device).
+hipError_t noalloc_scratch(void **ptr, size_t *bytes);
+
 // ---- batched on-chip kernel (perm_batch.hip) ----
 struct BatchChunk {
     uint32_t first;   // index into the sorted order

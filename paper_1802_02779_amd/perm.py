@@ -51,7 +51,7 @@ EXPORTS = [
     "perm_server_submit", "perm_server_poll", "perm_server_destroy", "perm_tuning_get",
     "perm_tuning_set", "perm_tuning_load", "perm_tuning_save", "perm_tuning_key",
     "perm_profile_enable", "perm_profile_read", "perm_multi_workspace_bytes", "perm_solve_multi",
-    "perm_solve_multi_async", "perm_multi_plan_info", "perm_probe_fp64",
+    "perm_solve_multi_async", "perm_multi_plan_info", "perm_probe_fp64", "perm_solve_async_noalloc",
     "perm_probe_int", "perm_bunched_workspace_bytes", "perm_bunched_orientation", "perm_solve_bunched",
 ]
 
@@ -149,6 +149,8 @@ def lib() -> ctypes.CDLL:
         L.perm_solve_bunched.restype = i32
         L.perm_probe_int.argtypes = [ctypes.POINTER(ctypes.c_double), ctypes.POINTER(ctypes.c_double), vp]
         L.perm_probe_int.restype = i32
+        L.perm_solve_async_noalloc.argtypes = [i32, vp, i64, vp, vp]
+        L.perm_solve_async_noalloc.restype = i32
         L.perm_ryser_workspace_bytes.argtypes = [i32, i32]
         L.perm_ryser_workspace_bytes.restype = sz
         L.perm_ryser.argtypes = [i32, i32, vp, i64, vp, vp, sz, vp]
@@ -281,6 +283,19 @@ def perm_solve_async(n: int, a_dev, lda: int, result_dev, workspace, stream=None
                                   result_dev.data_ptr(),
                                   workspace.data_ptr() if workspace is not None else None, ws_bytes,
                                   _stream_ptr(stream)))
+
+
+PERM_NOALLOC_N_MAX = 22
+PERM_NOALLOC_SCRATCH_BYTES = 24 << 20
+
+
+def perm_solve_async_noalloc(n: int, a_dev, lda: int, result_dev, stream=None) -> None:
+    """perm_solve_async without a workspace: the library's fixed device array
+    holds the tables (n <= PERM_NOALLOC_N_MAX; calls on one device must not
+    overlap)."""
+    _check(lib().perm_solve_async_noalloc(n, a_dev.data_ptr() if a_dev is not None else None, lda,
+                                          result_dev.data_ptr() if result_dev is not None else None,
+                                          _stream_ptr(stream)))
 
 
 def perm_ryser_workspace_bytes(dtype: int, n: int) -> int:
