@@ -123,6 +123,9 @@ def main():
                     help="comma list of extra sections to run (n26, ryser, n34, h2h, compare, int30, multi, int10, batch, "
                          "serving); "
                          "default: all")
+    ap.add_argument("--tune28", default="",
+                    help="override the n = 28 row of the tuning table: 't,remap,flags' (layer_t, "
+                         "layer_xcd_remap, layer_flags)")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="first copy 1 GiB device to device (a plain copy kernel of known size, "
                          "the reference for HBM byte counters)")
@@ -148,6 +151,12 @@ def main():
                 tuning = os.path.relpath(tuning_file, ROOT)
         except perm.PermError as e:
             log(f"tuning file ignored: {e}")
+    if args.tune28:
+        t28, r28, f28 = (int(x) for x in args.tune28.split(","))
+        tu = perm.perm_tuning_get()
+        tu.layer_t[28], tu.layer_xcd_remap[28], tu.layer_flags[28] = t28, r28, f28
+        perm.perm_tuning_set(tu)
+        tuning += f" with n = 28 row t={t28}, remap={r28}, flags={f28}"
     if args.copy_calibration:
         src = torch.empty(1 << 30, dtype=torch.uint8, device="cuda")
         dst = torch.empty_like(src)
@@ -190,14 +199,8 @@ def main():
     torch.cuda.synchronize()
     prof = perm.perm_profile_read()
     perm.perm_profile_enable(False)
-    # the sweep the shipped tuning picks for n = 28: the block sweep (one
-    # launch per high level) or the layer sweep (one launch per layer)
-    if prof.block_c128_launches:
-        kernel, launches, kern_ms = "k_block_c128", int(prof.block_c128_launches), prof.block_c128_ms
-        counters_file = os.path.join(ROOT, "profiles", "block_c128_n28_counters.json")
-    else:
-        kernel, launches, kern_ms = "k_layer_c128", int(prof.layer_c128_launches), prof.layer_c128_ms
-        counters_file = COUNTERS
+    kernel, launches, kern_ms = "k_layer_c128", int(prof.layer_c128_launches), prof.layer_c128_ms
+    counters_file = COUNTERS
     per_step = launches // args.steps
     avg_ms = kern_ms / max(launches, 1)
     # algorithmic bytes of one solve (every stored value written once and

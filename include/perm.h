@@ -391,12 +391,7 @@ int perm_server_destroy(perm_server_t *s);
  *                      consecutive tiles; 0 = hardware order, -1 = default.
  *   layer_flags[n]     bit 0: non-temporal stores of layer outputs;
  *                      bit 1: the exact integer sweep's plain 64-bit layers
- *                      (those bounded below 2^63) use layer_t + 1 low columns;
- *                      bit 2: complex orders 24..32 run the block sweep
- *                      instead of the layer sweep: one workgroup per high
- *                      part T holds F(T u L) for all 2^t low parts L (t =
- *                      min(layer_t, 13)), one launch per |T|; same values,
- *                      same chains, same bits.
+ *                      (those bounded below 2^63) use layer_t + 1 low columns.
  *   layer_thin[n]      tiles with fewer outputs than this are computed one
  *                      output per thread instead of staging a window in LDS;
  *                      0 = library default (128), -1 = never.
@@ -438,8 +433,6 @@ typedef struct {
     int64_t multi_c128_launches;
     double multi_modp_ms;   /* the same, residues */
     int64_t multi_modp_launches;
-    double block_c128_ms;   /* complex block sweep (layer_flags bit 2), per high-level launch */
-    int64_t block_c128_launches;
     int64_t int_plain_layers; /* layers of perm_solve's exact integer sweep run in plain
                                  64-bit arithmetic (counted once per run of the plain
                                  prefix, which serves every prime) */

@@ -3,7 +3,6 @@
 // sweep, so both are compiled together.
 #include "perm_layers.hip"
 #include "perm_layer_c128.hip"
-#include "perm_block_c128.hip"
 #include "perm_layer_modp.hip"
 #include "perm_batch.hip"
 #include "perm_ryser.hip"

@@ -420,30 +420,9 @@ static size_t max_layer(int n) {
     return m;
 }
 
-// Block sweep (perm_block_c128.hip): orders it serves and its low columns.
-constexpr int kBlockNMin = 24, kBlockNMax = 32, kBlockTMax = 13;
-
-static size_t block_level_bytes(int n, int t) {
-    const int nh = n - t;
-    return align256((size_t)binom_host(nh, nh / 2) * ((size_t)1 << t) * 16);
-}
-
-// Low columns of the block sweep for order n, 0 when it does not apply.
-static int block_t(int n) {
-    if (n < kBlockNMin || n > kBlockNMax || !(tuned_layer_flags(n) & 4)) return 0;
-    int t = tuned_layer_t(n);
-    if (t > kBlockTMax) t = kBlockTMax;
-    if (n - t > kHighBits) return 0;
-    return t;
-}
-
 size_t c128_workspace_bytes(int n) {
     if (n < 2) return 256;
-    size_t tables = 2 * align256(max_layer(n) * 16);
-    if (n >= kBlockNMin && n <= kBlockNMax)  // whichever sweep and low-column count the tuning picks
-        for (int t = std::max(1, n - kHighBits); t <= std::min(kBlockTMax, n); t++)
-            tables = std::max(tables, 2 * block_level_bytes(n, t));
-    return align256((size_t)n * n * 16) + 256 + tables;
+    return align256((size_t)n * n * 16) + 256 + 2 * align256(max_layer(n) * 16);
 }
 
 int solve_c128_device(int n, const void *a_dev, int64_t lda, void *result_dev, void *ws,
@@ -484,35 +463,6 @@ int solve_c128_device(int n, const void *a_dev, int64_t lda, void *result_dev, v
             (void)hipEventRecord(e1, s);
             profile_record(2, e0, e1);
         }
-        return PERM_OK;
-    }
-    const int tb = block_t(n);
-    if (tb) {
-        // block sweep: one launch per high level m, ping-pong by level
-        char *buf0 = base + align256((size_t)n * n * 16) + 256;
-        char *buf1 = buf0 + block_level_bytes(n, tb);
-        HIPCALL(launch_pack_c128(a_dev, lda, n, packed, buf1, s), "pack kernel");
-        const int chunk = tuned_layer_remap(n);
-        const bool prof = allow_profile && profiling_on();
-        char *cur = buf0;
-        for (int m = 0; m <= n - tb; m++) {
-            BlockArgs args;
-            plan_block(n, tb, m, chunk, &args);
-            cur = (m & 1) ? buf1 : buf0;
-            const char *prv = (m & 1) ? buf0 : buf1;
-            hipEvent_t e0 = nullptr, e1 = nullptr;
-            if (prof) {
-                e0 = profile_event();
-                e1 = profile_event();
-                if (e0) (void)hipEventRecord(e0, s);
-            }
-            HIPCALL(launch_block_c128(prv, cur, packed, args, s), "block kernel");
-            if (prof && e0 && e1) {
-                (void)hipEventRecord(e1, s);
-                profile_record(6, e0, e1);
-            }
-        }
-        HIPCALL(launch_block_readout_c128(cur, tb, result_dev, s), "readout kernel");
         return PERM_OK;
     }
     const size_t lay = align256(max_layer(n) * 16);
@@ -1346,7 +1296,7 @@ int perm_tuning_set(const perm_tuning_t *in) {
             return set_error(PERM_EINVAL, "layer_t[%d] = %d impossible", n, t);
         if (in->layer_xcd_remap[n] < -1 || in->layer_xcd_remap[n] > 4096)
             return set_error(PERM_EINVAL, "layer_xcd_remap[%d] = %d", n, in->layer_xcd_remap[n]);
-        if (in->layer_flags[n] & ~7)
+        if (in->layer_flags[n] & ~3)
             return set_error(PERM_EINVAL, "layer_flags[%d] = %d", n, in->layer_flags[n]);
         if (in->layer_thin[n] < -1 || in->layer_thin[n] > 65536)
             return set_error(PERM_EINVAL, "layer_thin[%d] = %d", n, in->layer_thin[n]);
@@ -1503,9 +1453,6 @@ int perm_profile_read(perm_profile_t *out) {
         } else if (e.kind == 4) {
             out->multi_c128_ms += ms;
             out->multi_c128_launches++;
-        } else if (e.kind == 6) {
-            out->block_c128_ms += ms;
-            out->block_c128_launches++;
         } else {
             out->multi_modp_ms += ms;
             out->multi_modp_launches++;

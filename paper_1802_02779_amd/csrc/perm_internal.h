@@ -138,25 +138,6 @@ hipError_t launch_readout_modp(const uint64_t *last, size_t plane, int rp, uint6
 hipError_t launch_int64_to_modp(const uint64_t *src, uint64_t *dst, size_t plane, size_t count,
                                 const uint64_t *primes, int rp, hipStream_t s);
 
-// ---- block sweep (perm_block_c128.hip) ----
-// A block holds F(T u L) for one high part T (|T| = m, columns >= t) and all
-// 2^t low parts L, ordered by |L| then colex rank of L; the blocks of level m
-// are stored back to back in colex order of T.  One launch per level m.
-constexpr int kBlockThreads = 256;
-struct BlockArgs {
-    int n, t, m;
-    uint32_t nblocks;               // C(n - t, m)
-    uint32_t high_off;              // g_highlist offset of the m-subsets
-    uint32_t chunk;                 // XCD runs of consecutive blocks (0 = hardware order)
-    uint32_t lds_level;             // C(t, t/2): entries of the largest low level
-    uint32_t loff[kTMax + 2];       // first position of low level k' in a block
-    uint32_t low_off[kTMax + 1];    // lowtab offset of (t, k')
-};
-uint32_t plan_block(int n, int t, int m, int chunk, BlockArgs *a);
-size_t block_lds_bytes_c128(const BlockArgs &a);
-hipError_t launch_block_c128(const void *prev, void *cur, const void *packed, const BlockArgs &a, hipStream_t s);
-hipError_t launch_block_readout_c128(const void *last, int t, void *result, hipStream_t s);
-
 // ---- allocation-free solve (perm_noalloc.hip) ----
 // Device address and size of the file-scope scratch array on the current
 // device (looked up once per device).

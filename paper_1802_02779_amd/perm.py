@@ -111,7 +111,6 @@ class perm_profile_t(ctypes.Structure):
                 ("ryser_ms", ctypes.c_double), ("ryser_launches", ctypes.c_int64),
                 ("multi_c128_ms", ctypes.c_double), ("multi_c128_launches", ctypes.c_int64),
                 ("multi_modp_ms", ctypes.c_double), ("multi_modp_launches", ctypes.c_int64),
-                ("block_c128_ms", ctypes.c_double), ("block_c128_launches", ctypes.c_int64),
                 ("int_plain_layers", ctypes.c_int64)]
 
 

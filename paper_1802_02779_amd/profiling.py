@@ -34,20 +34,6 @@ def main():
     if multi:
         multi_layers(cur)
         return
-    blk = list(cur.execute("select duration, grid_x, workgroup_x, lds_size from kernels "
-                           "where name like '%k_block_c128%' order by start"))
-    bt = int(sys.argv[4]) if len(sys.argv) > 4 else 12
-    if len(blk) >= n - bt + 1:
-        nh = n - bt
-        print(f"\nlast step, complex block sweep, n = {n}, t = {bt} (blocks of 2^{bt} values):\n")
-        print("| level m | us | blocks | LDS bytes | algorithmic GB/s |")
-        print("|---|---|---|---|---|")
-        tot = 0
-        for m, (d, g, wg, lds) in zip(range(nh + 1), blk[-(nh + 1):]):
-            by = 16 * 2 ** bt * (math.comb(nh, m) + (math.comb(nh, m - 1) if m else 0))
-            tot += d
-            print(f"| {m} | {d / 1000:.1f} | {g // wg} | {lds} | {by / d:.0f} |")
-        print(f"\nsum of the step's block launches: {tot / 1e6:.3f} ms")
     rows = list(cur.execute("select duration, grid_x, workgroup_x, lds_size from kernels "
                             "where name like '%k_layer_c128%' order by start"))
     if len(rows) >= n - 1:
@@ -90,13 +76,14 @@ def multi_layers(cur):
 def source_hash(root: str, n: int = 28) -> str:
     """Hash of what decides the complex layer sweep's memory traffic at order
     n: its kernel sources and the order-n entries of the shipped tuning file.
-    Counter data is valid only while this hash is unchanged."""
+    Counter data is valid only while this hash is unchanged (declarations in
+    shared headers are not part of it)."""
     import hashlib
     import json
     import os
     h = hashlib.sha256()
     csrc = os.path.join(root, "paper_1802_02779_amd", "csrc")
-    for f in ("perm_layers.hip", "perm_layer_c128.hip", "perm_block_c128.hip", "perm_internal.h"):
+    for f in ("perm_layers.hip", "perm_layer_c128.hip"):
         with open(os.path.join(csrc, f), "rb") as fh:
             h.update(fh.read())
     tfile = os.path.join(root, "paper_1802_02779_amd", "tuning", "gfx950.json")
@@ -110,14 +97,13 @@ def source_hash(root: str, n: int = 28) -> str:
 
 def int_source_hash(root: str, n: int = 30) -> str:
     """Hash of what decides the integer sweep's memory traffic at order n:
-    its kernel and host sources and the order-n row of the shipped tuning
-    file."""
+    its kernel sources and the order-n row of the shipped tuning file."""
     import hashlib
     import json
     import os
     h = hashlib.sha256()
     csrc = os.path.join(root, "paper_1802_02779_amd", "csrc")
-    for f in ("perm_layers.hip", "perm_layer_modp.hip", "perm_internal.h", "perm_host.cpp"):
+    for f in ("perm_layers.hip", "perm_layer_modp.hip"):
         with open(os.path.join(csrc, f), "rb") as fh:
             h.update(fh.read())
     tfile = os.path.join(root, "paper_1802_02779_amd", "tuning", "gfx950.json")
@@ -127,56 +113,6 @@ def int_source_hash(root: str, n: int = 30) -> str:
         row = [t.get(k, [0] * (n + 1))[n] for k in ("layer_t", "layer_xcd_remap", "layer_flags", "layer_thin")]
         h.update(repr(row).encode())
     return h.hexdigest()[:16]
-
-
-def block_counters(fetch_db: str, write_db: str, hit_db: str, cmd: str, root: str, n: int = 28, t: int = 12):
-    """HBM traffic of the complex block sweep (one launch per high level
-    m = 0..n-t, the last solve in the run) from three rocprofv3 --pmc runs,
-    scaled by the 1 GiB copy each run starts with.  Per level: algorithmic
-    bytes = the level's values written once plus the previous level's read
-    once.  Returns (markdown, json-able dict)."""
-    import collections
-    nh = n - t
-
-    def load(db):
-        cur = sqlite3.connect(db).cursor()
-        rows = list(cur.execute("select dispatch_id, kernel_name, grid_size, counter_name, value "
-                                "from counters_collection order by dispatch_id"))
-        cal, per = {}, collections.OrderedDict()
-        for d, k, g, c, v in rows:
-            if "copyBuffer" in k and g == 131072:
-                cal[c] = v
-            if "k_block_c128" in k:
-                per.setdefault(d, {})[c] = v
-        return cal, list(per.values())[-(nh + 1):]
-
-    fcal, fl = load(fetch_db)
-    wcal, wl = load(write_db)
-    _, hl = load(hit_db)
-    ff = 1048576.0 / fcal["FETCH_SIZE"]
-    wf = 1048576.0 / wcal["WRITE_SIZE"]
-    lines = [f"commands:\n\n    {cmd}\n",
-             f"calibration (1 GiB device copy): FETCH_SIZE factor {ff:.4f}, WRITE_SIZE factor {wf:.4f}\n",
-             f"block sweep, n = {n}, t = {t}: blocks of 2^{t} values, one launch per high level m\n",
-             "| level m | blocks | algorithmic read MB | fetched MB | algorithmic write MB | written MB | L2 hit |",
-             "|---|---|---|---|---|---|---|"]
-    tf = tw = ta = hits = misses = 0.0
-    for i, m in enumerate(range(nh + 1)):
-        ar = 16 * math.comb(nh, m - 1) * 2 ** t if m >= 1 else 0
-        aw = 16 * math.comb(nh, m) * 2 ** t
-        f = fl[i]["FETCH_SIZE"] * 1024 * ff
-        w = wl[i]["WRITE_SIZE"] * 1024 * wf
-        h, mi = hl[i]["TCC_HIT_sum"], hl[i]["TCC_MISS_sum"]
-        tf, tw, ta, hits, misses = tf + f, tw + w, ta + ar + aw, hits + h, misses + mi
-        lines.append(f"| {m} | {math.comb(nh, m)} | {ar / 1e6:.1f} | {f / 1e6:.1f} | {aw / 1e6:.1f} | {w / 1e6:.1f} | "
-                     f"{h / max(h + mi, 1):.3f} |")
-    lines.append(f"\nper step: fetched {tf / 1e9:.2f} GB, written {tw / 1e9:.2f} GB, algorithmic "
-                 f"{ta / 1e9:.2f} GB, amplification {(tf + tw) / ta:.2f}, L2 hit rate {hits / (hits + misses):.3f}")
-    data = {"source_hash": source_hash(root), "n": n, "t": t, "launches": nh + 1,
-            "hbm_bytes_per_launch": int((tf + tw) / (nh + 1)), "fetch_bytes_per_step": int(tf),
-            "write_bytes_per_step": int(tw), "algorithmic_bytes_per_step": int(ta),
-            "fetch_factor": ff, "write_factor": wf}
-    return "\n".join(lines) + "\n", data
 
 
 def modp_counters(fetch_db: str, write_db: str, hit_db: str, cmd: str, root: str, n: int = 30):
@@ -373,6 +309,47 @@ def kernel_counters(fetch_db: str, write_db: str, hit_db: str, cmd: str, kernel:
             f"{(tf + tw) / algorithmic_bytes:.2f}, L2 hit rate {hits / max(hits + misses, 1):.3f}\n")
 
 
+def batch_sq_counters(dbs, cmd: str) -> str:
+    """SQ / GRBM counters of the persistent batched launch (the last
+    k_batch_c128 dispatch with more than one workgroup) from one or more
+    rocprofv3 --pmc runs, with the ratios that say where its cycles go."""
+    vals = {}
+    for db in dbs:
+        cur = sqlite3.connect(db).cursor()
+        rows = list(cur.execute("select dispatch_id, kernel_name, grid_size, counter_name, value "
+                                "from counters_collection order by dispatch_id"))
+        last = {}
+        for d, k, g, c, v in rows:
+            if "k_batch_c128" in k and g > 4096:  # the persistent launch, not a single-matrix one
+                last.setdefault(d, {})[c] = v
+        if last:
+            vals.update(last[max(last)])
+    lines = [f"commands:\n\n    {cmd}\n", "persistent k_batch_c128 launch over the 2^20 mixed batch:\n",
+             "| counter | value |", "|---|---|"]
+    for c in sorted(vals):
+        lines.append(f"| {c} | {vals[c]:.4g} |")
+    def ratio(a, b):
+        return vals[a] / vals[b] if a in vals and b in vals and vals[b] else None
+    derived = [("SQ_WAIT_ANY / SQ_WAVE_CYCLES (waves waiting on anything)", ratio("SQ_WAIT_ANY", "SQ_WAVE_CYCLES")),
+               ("SQ_ACTIVE_INST_VALU / SQ_WAVE_CYCLES", ratio("SQ_ACTIVE_INST_VALU", "SQ_WAVE_CYCLES")),
+               ("SQ_ACTIVE_INST_LDS / SQ_WAVE_CYCLES", ratio("SQ_ACTIVE_INST_LDS", "SQ_WAVE_CYCLES")),
+               ("SQ_LDS_BANK_CONFLICT / SQ_ACTIVE_INST_LDS", ratio("SQ_LDS_BANK_CONFLICT", "SQ_ACTIVE_INST_LDS")),
+               ("SQ_INSTS_LDS / SQ_INSTS_VALU", ratio("SQ_INSTS_LDS", "SQ_INSTS_VALU")),
+               ("SQ_INSTS_VALU_FMA_F64 / SQ_INSTS_VALU", ratio("SQ_INSTS_VALU_FMA_F64", "SQ_INSTS_VALU")),
+               ("SQ_WAVE_CYCLES / SQ_BUSY_CYCLES (resident waves per busy cycle)",
+                ratio("SQ_WAVE_CYCLES", "SQ_BUSY_CYCLES"))]
+    lines.append("\n| ratio | value |\n|---|---|")
+    for name, v in derived:
+        if v is not None:
+            lines.append(f"| {name} | {v:.3f} |")
+    return "\n".join(lines) + "\n"
+
+
+if __name__ == "__main__" and len(sys.argv) > 1 and sys.argv[1] == "batch-sq":
+    # "command" db [db ...]
+    print(batch_sq_counters(sys.argv[3:], sys.argv[2]))
+
+
 if __name__ == "__main__" and len(sys.argv) > 1 and sys.argv[1] == "kernel-counters":
     # fetch.db write.db hit.db "command" kernel launches algorithmic_bytes "workload"
     print(kernel_counters(sys.argv[2], sys.argv[3], sys.argv[4], sys.argv[5], sys.argv[6], int(sys.argv[7]),
@@ -403,23 +380,17 @@ if __name__ == "__main__" and len(sys.argv) > 1 and sys.argv[1] == "counters":
         json.dump(data, f, indent=1)
 
 
-if __name__ == "__main__" and len(sys.argv) > 1 and sys.argv[1] in ("block-counters", "modp-counters"):
+if __name__ == "__main__" and len(sys.argv) > 1 and sys.argv[1] == "modp-counters":
     import json
     import os
     root = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
-    if sys.argv[1] == "block-counters":
-        # fetch.db write.db hit.db "command" t
-        md, data = block_counters(sys.argv[2], sys.argv[3], sys.argv[4], sys.argv[5], root, 28, int(sys.argv[6]))
-        name = "block_c128_n28_counters.json"
-    else:
-        md, data = modp_counters(sys.argv[2], sys.argv[3], sys.argv[4], sys.argv[5], root)
-        name = "layer_modp_n30_counters.json"
+    md, data = modp_counters(sys.argv[2], sys.argv[3], sys.argv[4], sys.argv[5], root)
     print(md)
-    with open(os.path.join(root, "profiles", name), "w") as f:
+    with open(os.path.join(root, "profiles", "layer_modp_n30_counters.json"), "w") as f:
         json.dump(data, f, indent=1)
 
 
 if __name__ == "__main__" and not (len(sys.argv) > 1 and sys.argv[1] in ("counters", "multi-counters",
-                                                                       "kernel-counters", "block-counters",
-                                                                       "modp-counters")):
+                                                                       "kernel-counters", "modp-counters",
+                                                                       "batch-sq")):
     main()

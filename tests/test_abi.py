@@ -56,9 +56,6 @@ def test_workspace_bytes(perm):
         b = perm.perm_workspace_bytes(perm.PERM_COMPLEX128, n)
         maxc = max(comb(n, k) for k in range(n + 1))
         tables = 2 * 16 * maxc
-        if 24 <= n <= 32:  # the block sweep: two levels of blocks of 2^t values
-            tables = max([tables] + [2 * 16 * comb(n - t, (n - t) // 2) * 2 ** t
-                                     for t in range(max(1, n - 22), 14)])
         assert b >= tables + 16 * n * n
         assert b < tables + 16 * n * n + 4096
         bi = perm.perm_workspace_bytes(perm.PERM_INT64, n)
@@ -66,9 +63,8 @@ def test_workspace_bytes(perm):
     assert perm.perm_workspace_bytes(perm.PERM_COMPLEX128, 35) == 0
     assert perm.perm_workspace_bytes(perm.PERM_COMPLEX128, -1) == 0
     assert perm.perm_workspace_bytes(7, 5) == 0
-    # n = 28 complex: room for the block sweep, two levels of C(16, 8) blocks
-    # of 2^12 values (or C(15, 7) of 2^13), about 1.69 GB
-    assert abs(perm.perm_workspace_bytes(perm.PERM_COMPLEX128, 28) - 2 * 16 * comb(16, 8) * 4096) < 1e5
+    # n = 28 complex: two layer tables of C(28,14) entries, about 1.28 GB
+    assert abs(perm.perm_workspace_bytes(perm.PERM_COMPLEX128, 28) - 2 * 16 * comb(28, 14)) < 1e5
 
 
 def test_argument_errors_before_any_device_work(perm):
@@ -122,16 +118,16 @@ def test_tuning_validation(perm):
     with pytest.raises(perm.PermError):
         perm.perm_tuning_set(t)
     t = perm.perm_tuning_t.from_buffer_copy(saved)
-    t.layer_flags[24] = 8  # only bits 0, 1 and 2 are defined
+    t.layer_flags[24] = 4  # only bits 0 and 1 are defined
     with pytest.raises(perm.PermError):
         perm.perm_tuning_set(t)
     t = perm.perm_tuning_t.from_buffer_copy(saved)
     t.layer_t[28] = 13
-    t.layer_flags[28] = 7
+    t.layer_flags[28] = 3
     t.batch_group[12] = 128
     perm.perm_tuning_set(t)
     assert perm.perm_tuning_get().layer_t[28] == 13
-    assert perm.perm_tuning_get().layer_flags[28] == 7
+    assert perm.perm_tuning_get().layer_flags[28] == 3
     perm.perm_tuning_set(saved)
 
 

@@ -408,28 +408,3 @@ def test_full_sizes_under_shipped_tuning(P, golden):
     finally:
         P.perm_tuning_set(saved)
         torch.cuda.empty_cache()
-
-
-@pytest.mark.parametrize("n", [24, 25, 26, 27, 28, 29, 30])
-def test_block_sweep_bitwise(P, golden, n):
-    """Bit 2 of layer_flags runs the block sweep (one workgroup per high
-    part, all low parts of all popcounts, one launch per high level): the
-    same stored values and chains, so the same bits as the oracle, for
-    several low-column counts and XCD run lengths."""
-    g = golden[f"c128_n{n}_s0"]
-    want = (int(g["re_bits"], 16), int(g["im_bits"], 16))
-    A = inputs.complex_gaussian(n, seed=0)
-    saved = P.perm_tuning_get()
-    try:
-        for t, remap in ((12, 64), (13, 8), (11, 0), (10, 3)):
-            if n - t > 22:
-                continue
-            tu = P.perm_tuning_t.from_buffer_copy(saved)
-            tu.layer_t[n] = t
-            tu.layer_xcd_remap[n] = remap
-            tu.layer_flags[n] = 4
-            P.perm_tuning_set(tu)
-            print(f"[gpu] block sweep n={n} t={t} remap={remap}", flush=True)
-            assert c_bits(P.perm_solve(A)) == want, (n, t, remap)
-    finally:
-        P.perm_tuning_set(saved)
