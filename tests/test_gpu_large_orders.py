@@ -120,3 +120,24 @@ def test_complex_rank_one_n34(P):
     # per(|A|) = |ref| for a rank-one matrix; the chain bound plus the
     # rounding of the reference itself (2n products)
     assert abs(z - ref) <= (chain_error_bound(n) + 4 * n * U64) * abs(ref)
+
+
+@pytest.mark.parametrize("n", [31, 32, 33, 34])
+def test_complex_exact_on_sparse_integer_matrices(P, n):
+    """0/1 matrices with at most three ones per row (the diagonal, the
+    superdiagonal and, from the third row on, one random column): every
+    stored value is an integer bounded by the product of the row sums,
+    4 * 3^32 < 2^53, so the complex sweep's fp64 chain is exact and must give
+    the integer permanent bit for bit -- an exact pin of the complex path's
+    tables and indexing at orders beyond the oracle's tables."""
+    rng = np.random.default_rng(100 + n)
+    A = np.eye(n, dtype=np.int64)
+    A[np.arange(n - 1), np.arange(1, n)] = 1
+    A[np.arange(2, n), rng.integers(0, n, size=n - 2)] = 1
+    assert math.prod(int(r) for r in A.sum(axis=1)) < 2 ** 53
+    print(f"[gpu] sparse 0/1 n={n}: integer and complex sweeps", flush=True)
+    want = P.perm_solve(A)
+    assert want == P.perm_ryser(A)
+    assert 0 < want < 2 ** 53
+    z = P.perm_solve(A.astype(np.complex128))
+    assert z == complex(float(want), 0.0), (z, want)
