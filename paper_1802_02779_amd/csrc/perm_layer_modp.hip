@@ -201,6 +201,22 @@ __global__ __launch_bounds__(kLayerBlock) void k_layer_modp(const uint64_t *__re
         u128 acc[RP];
 #pragma unroll
         for (int r = 0; r < RP; r++) acc[r] = 0;
+        // Integer sums are exact in any order, so on the add-only path with
+        // one plane (the plain 64-bit layers of a 0/1 row, most of a 0/1
+        // solve) the loads of the first eight active high windows (HBM) are
+        // issued before the low terms (rank table, then LDS) and arrive
+        // while those run (n = 30 0/1: 12.39 -> 12.12 ms).  With products or
+        // more planes the registers this takes cost more than the overlap
+        // gains (26x26 entries 0..9: 3.27 -> 3.47 ms), so there the windows
+        // are read after the low terms.
+        constexpr int kPre = (RP == 1 && BIN) ? 8 : 0;
+        uint64_t hw[kPre > 0 ? kPre : 1][RP];
+#pragma unroll
+        for (int u = 0; u < kPre; u++)
+            if (u < mact) {
+#pragma unroll
+                for (int r = 0; r < RP; r++) hw[u][r] = prev[(size_t)r * plane + s_hb[u] + rr];
+            }
         // low columns: rank-table entries four at a time, then the LDS terms
         int p = 0;
         for (; p + 4 <= ti.kp; p += 4) {
@@ -234,9 +250,15 @@ __global__ __launch_bounds__(kLayerBlock) void k_layer_modp(const uint64_t *__re
                 for (int r = 0; r < RP; r++) acc[r] += (u128)s_arow[r * t + col] * s_win[r * W + idx];
             }
         }
-        // active high windows, aligned with the tile: four windows' loads
-        // (all primes) in flight before they are added
-        int q = 0;
+        // the prefetched high windows, then the rest four at a time
+#pragma unroll
+        for (int u = 0; u < kPre; u++)
+            if (u < mact) {
+#pragma unroll
+                for (int r = 0; r < RP; r++)
+                    acc[r] += BIN ? (u128)hw[u][r] : (u128)s_ha[r * 32 + u] * hw[u][r];
+            }
+        int q = kPre;
         for (; q + 4 <= mact; q += 4) {
             uint64_t w[4][RP];
 #pragma unroll
