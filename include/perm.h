@@ -303,6 +303,20 @@ int perm_probe_fp64(double *tflops, void *stream);
  * failure. */
 int perm_probe_int(double *mac_fold_gops, double *add64_gops, void *stream);
 
+/* Inspection of the cache-aware tile order (layer_flags bit 2).  The list
+ * that a tiled layer launch reads for layer k (2..n) of order n with a low
+ * window of t columns: in workgroup order, the high part of each workgroup's
+ * tile as a mask of the n - t high columns (bit i = column t + i), or
+ * 0xffffffff for an empty padding slot; the tiled k' groups in increasing
+ * k', each padded to a multiple of 8 slots.  value_bytes is the size of one
+ * stored value (16 for the complex sweep, 8 per prime for the integer
+ * sweep); it sets how many high columns a family of tiles may span.  Uses
+ * the tuning table's XCD run length and thin-tile threshold for n.  Host
+ * only: no device call.  Writes min(cap, length) entries to out (which may
+ * be null when cap is 0) and the length to *len.  PERM_EINVAL for a null
+ * len, n - t above 18, or n, t, k or value_bytes out of range. */
+int perm_layer_tile_order(int n, int t, int k, int value_bytes, uint32_t *out, size_t cap, size_t *len);
+
 /* Device workspace bytes for a batch (host array ns of `count` orders). */
 size_t perm_batch_workspace_bytes(perm_dtype_t dt, int count, const int32_t *ns);
 
@@ -391,7 +405,15 @@ int perm_server_destroy(perm_server_t *s);
  *                      consecutive tiles; 0 = hardware order, -1 = default.
  *   layer_flags[n]     bit 0: non-temporal stores of layer outputs;
  *                      bit 1: the exact integer sweep's plain 64-bit layers
- *                      (those bounded below 2^63) use layer_t + 1 low columns.
+ *                      (those bounded below 2^63) use layer_t + 1 low columns;
+ *                      bit 2: cache-aware tile order (both sweeps, orders
+ *                      with at most 18 high columns): tiles that share high
+ *                      windows are dealt to one XCD together (see
+ *                      perm_layer_tile_order).  The first solve of an order
+ *                      with this bit builds the order on the host and uploads
+ *                      it into library-owned device memory (an allocation
+ *                      and a stream synchronization, once per device, order
+ *                      and schedule); perm_solve_async_noalloc never uses it.
  *   layer_thin[n]      tiles with fewer outputs than this are computed one
  *                      output per thread instead of staging a window in LDS;
  *                      0 = library default (128), -1 = never.

@@ -9,7 +9,9 @@ parameter here only changes the schedule, so any difference would be a bug and
 disqualifies the candidate):
 
 * layer sweep (perm_solve_async, complex128): low-window width t, XCD chunk
-  of the tile order, non-temporal output stores, per-thread threshold;
+  of the tile order, non-temporal output stores, per-thread threshold, and
+  then, on the winning schedule, the cache-aware tile order (bit 2 of
+  layer_flags, which the exact integer sweep of that order uses too);
 * exact integer sweep (perm_solve, int64 Bernoulli input): whether its plain
   64-bit layers take one low column more than the complex sweep (bit 1 of
   layer_flags; the values must come out identical);
@@ -32,6 +34,7 @@ import numpy as np
 HERE = os.path.dirname(os.path.abspath(__file__))
 DEFAULT_FILE = os.path.join(HERE, "tuning", "gfx950.json")
 HIGH_BITS = 22  # the library's largest tile high part: n - t above it is rejected
+ORDER_HIGH_BITS = 18  # largest high part the cache-aware tile order covers
 
 
 def _time_ms(fn, reps: int, sync) -> float:
@@ -43,6 +46,25 @@ def _time_ms(fn, reps: int, sync) -> float:
         fn()
         sync()
         ts.append((time.perf_counter() - t0) * 1000.0)
+    return float(np.median(ts))
+
+
+def _time_events_ms(fn, reps: int, torch, inner: int) -> float:
+    """Median over reps of the mean device time of `inner` back-to-back calls
+    of an asynchronous fn, from events on the current stream (host launch
+    overhead and synchronization stay out of the figure)."""
+    fn()
+    torch.cuda.synchronize()
+    ts = []
+    for _ in range(reps):
+        e0 = torch.cuda.Event(enable_timing=True)
+        e1 = torch.cuda.Event(enable_timing=True)
+        e0.record()
+        for _ in range(inner):
+            fn()
+        e1.record()
+        torch.cuda.synchronize()
+        ts.append(e0.elapsed_time(e1) / inner)
     return float(np.median(ts))
 
 
@@ -60,11 +82,13 @@ def tune_layer(perm, inputs, torch, n: int, log=_log, reps: int = 3):
     default = perm.perm_tuning_t.from_buffer_copy(base)
     default.layer_t[n] = 0
     default.layer_xcd_remap[n] = -1
-    default.layer_flags[n] = base.layer_flags[n] & ~1  # bit 0 is this sweep's; other bits are kept
+    default.layer_flags[n] = base.layer_flags[n] & ~5  # bits 0 and 2 are this sweep's; bit 1 is kept
     default.layer_thin[n] = 0
     perm.perm_tuning_set(default)
     run = lambda: perm.perm_solve_async(n, d_a, n, d_r, ws)  # noqa: E731
-    ref_ms = _time_ms(run, reps, torch.cuda.synchronize)
+    inner = 10 if n <= 28 else 4
+    timed = lambda: _time_events_ms(run, reps, torch, inner)  # noqa: E731
+    ref_ms = timed()
     ref = d_r.cpu().numpy().view(np.uint64).copy()
     best = (ref_ms, 0, -1, 0, 0)
     # above n = 30 one solve takes 40-400 ms: a smaller grid
@@ -78,22 +102,36 @@ def tune_layer(perm, inputs, torch, n: int, log=_log, reps: int = 3):
                     cand = perm.perm_tuning_t.from_buffer_copy(default)
                     cand.layer_t[n] = t
                     cand.layer_xcd_remap[n] = chunk
-                    cand.layer_flags[n] = (default.layer_flags[n] & ~1) | nt
+                    cand.layer_flags[n] = default.layer_flags[n] | nt
                     cand.layer_thin[n] = thin
                     perm.perm_tuning_set(cand)
-                    ms = _time_ms(run, reps, torch.cuda.synchronize)
+                    ms = timed()
                     same = (d_r.cpu().numpy().view(np.uint64) == ref).all()
                     if not same:
                         log(f"  n={n} t={t} chunk={chunk} nt={nt} thin={thin}: result differs, rejected")
                         continue
                     if ms < best[0]:
                         best = (ms, t, chunk, nt, thin)
+    # the cache-aware tile order on the winning schedule
+    order = 0
+    t_eff = best[1] or min(12, max(6, n - 12))
+    if n - t_eff <= ORDER_HIGH_BITS:
+        cand = perm.perm_tuning_t.from_buffer_copy(default)
+        (cand.layer_t[n], cand.layer_xcd_remap[n], cand.layer_thin[n]) = best[1], best[2], best[4]
+        cand.layer_flags[n] = default.layer_flags[n] | best[3] | 4
+        perm.perm_tuning_set(cand)
+        ms = timed()
+        same = (d_r.cpu().numpy().view(np.uint64) == ref).all()
+        log(f"  n={n} cache-aware tile order: {ms:.3f} ms" + ("" if same else ", result differs, rejected"))
+        if same and ms < best[0]:
+            order = 4
+            best = (ms,) + best[1:]
     final = perm.perm_tuning_t.from_buffer_copy(base)
     (final.layer_t[n], final.layer_xcd_remap[n], final.layer_thin[n]) = best[1], best[2], best[4]
-    final.layer_flags[n] = (final.layer_flags[n] & ~1) | best[3]
+    final.layer_flags[n] = (final.layer_flags[n] & ~5) | best[3] | order
     perm.perm_tuning_set(final)
     log(f"layer n={n}: default {ref_ms:.3f} ms -> t={best[1]} chunk={best[2]} nt={best[3]} "
-        f"thin={best[4]} {best[0]:.3f} ms")
+        f"thin={best[4]} order={order >> 2} {best[0]:.3f} ms")
     return best
 
 

@@ -21,7 +21,7 @@ LIB_DIR = os.path.join(HERE, "_lib")
 LIB_PATH = os.path.join(LIB_DIR, "libpermgpu.so")
 INCLUDE = os.path.join(os.path.dirname(HERE), "include")
 
-SOURCES = ["perm_device.hip", "perm_host.cpp", "perm_server.cpp", "perm_multi.cpp"]
+SOURCES = ["perm_device.hip", "perm_host.cpp", "perm_server.cpp", "perm_multi.cpp", "perm_order.cpp"]
 ARCH = os.environ.get("PERM_OFFLOAD_ARCH", "gfx950")
 
 

@@ -426,7 +426,7 @@ size_t c128_workspace_bytes(int n) {
 }
 
 int solve_c128_device(int n, const void *a_dev, int64_t lda, void *result_dev, void *ws,
-                      size_t ws_bytes, hipStream_t s, bool allow_profile) {
+                      size_t ws_bytes, hipStream_t s, bool allow_profile, bool allow_order) {
     if (n == 0) {
         static const perm_c128_t one = {1.0, 0.0};
         HIPCALL(hipMemcpyAsync(result_dev, &one, sizeof one, hipMemcpyHostToDevice, s), "hipMemcpyAsync");
@@ -472,11 +472,17 @@ int solve_c128_device(int n, const void *a_dev, int64_t lda, void *result_dev, v
     const int t = tuned_layer_t(n);
     const int chunk = tuned_layer_remap(n);
     const int nt = tuned_layer_flags(n) & 1;
+    const uint32_t thin = tuned_layer_thin(n);
+    const bool order = allow_order && (tuned_layer_flags(n) & 4) && n - t <= kOrderNhMax;
     const bool prof = allow_profile && profiling_on();
     char *prev = buf0, *next = buf1;
     for (int k = 2; k <= n; k++) {
         LayerArgs args;
-        const uint32_t grid = plan_layer(n, k, t, chunk, nt, tuned_layer_thin(n), &args);
+        const uint32_t grid = plan_layer(n, k, t, chunk, nt, thin, &args, order);
+        if (order) {
+            const int orc = apply_tile_order(n, k, t, thin, chunk, 16, s, &args);
+            if (orc) return orc;
+        }
         hipEvent_t e0 = nullptr, e1 = nullptr;
         if (prof) {
             e0 = profile_event();
@@ -572,9 +578,16 @@ static int solve_int(int n, const int64_t *a, int64_t lda, perm_int_t *out, void
     // layers 2..K in plain 64-bit arithmetic (one plane), then residues
     const int K = d_plain ? plain_int64_layers(n, packed.data()) : 0;
     const int t_plain = tuned_plain_layer_t(n);
+    const uint32_t thin = tuned_layer_thin(n);
+    const bool order_on = tuned_layer_flags(n) & 4;
     auto layer = [&](uint64_t *prev, uint64_t *next, int k, const uint64_t *primes, int cnt, int tk) -> int {
         LayerArgs args;
-        const uint32_t grid = plan_layer(n, k, tk, chunk, 0, tuned_layer_thin(n), &args);
+        const bool order = order_on && n - tk <= kOrderNhMax;
+        const uint32_t grid = plan_layer(n, k, tk, chunk, 0, thin, &args, order);
+        if (order) {
+            const int orc = apply_tile_order(n, k, tk, thin, chunk, 8 * cnt, s, &args);
+            if (orc) return orc;
+        }
         args.binary_row = binary[k - 1];
         hipEvent_t e0 = nullptr, e1 = nullptr;
         if (prof) {
@@ -1178,7 +1191,7 @@ int perm_solve_async_noalloc(int n, const perm_c128_t *a_dev, int64_t lda, perm_
             return set_error(PERM_EDEVICE, "internal error: order %d needs %zu scratch bytes, the array holds %zu", n,
                              c128_workspace_bytes(n), ws_bytes);
         // profiling events are not created here: hipEventCreate allocates
-        return solve_c128_device(n, a_dev, lda, result_dev, ws, ws_bytes, (hipStream_t)stream, false);
+        return solve_c128_device(n, a_dev, lda, result_dev, ws, ws_bytes, (hipStream_t)stream, false, false);
     } catch (...) {
         return set_error(PERM_EDEVICE, "internal error");
     }
@@ -1296,7 +1309,7 @@ int perm_tuning_set(const perm_tuning_t *in) {
             return set_error(PERM_EINVAL, "layer_t[%d] = %d impossible", n, t);
         if (in->layer_xcd_remap[n] < -1 || in->layer_xcd_remap[n] > 4096)
             return set_error(PERM_EINVAL, "layer_xcd_remap[%d] = %d", n, in->layer_xcd_remap[n]);
-        if (in->layer_flags[n] & ~3)
+        if (in->layer_flags[n] & ~7)
             return set_error(PERM_EINVAL, "layer_flags[%d] = %d", n, in->layer_flags[n]);
         if (in->layer_thin[n] < -1 || in->layer_thin[n] > 65536)
             return set_error(PERM_EINVAL, "layer_thin[%d] = %d", n, in->layer_thin[n]);

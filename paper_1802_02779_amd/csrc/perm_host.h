@@ -28,8 +28,23 @@ uint32_t tuned_layer_thin(int n);
 int tuned_batch_group(int n, size_t lds_bytes, int elem_bytes, int block);
 
 // Complex solve of a device matrix into a device result, stream-ordered.
+// allow_order: the cache-aware tile order may be used (its first use for an
+// order builds and uploads a table, which allocates).
 int solve_c128_device(int n, const void *a_dev, int64_t lda, void *result_dev, void *ws,
-                      size_t ws_bytes, hipStream_t s, bool allow_profile = true);
+                      size_t ws_bytes, hipStream_t s, bool allow_profile = true, bool allow_order = true);
+
+// Cache-aware tile order of the layer sweep (perm_order.cpp).
+// z of the families of group (m high columns, tiles of ck outputs of
+// value_bytes each) for nh high columns; 0: colex runs.
+int order_z(int nh, int m, uint32_t ck, int value_bytes);
+// Appends layer k's padded, interleaved tile list (all tiled groups) to out;
+// false if building it failed (host memory).
+bool tile_order_layer(int n, int k, int t, uint32_t thin, int chunk, int value_bytes,
+                      std::vector<uint32_t> &out);
+// Points a (planned with pad8) at the device copy of the order, building and
+// uploading it on the first use of (device, n, t, thin, chunk, value_bytes).
+int apply_tile_order(int n, int k, int t, uint32_t thin, int chunk, int value_bytes, hipStream_t s,
+                     LayerArgs *a);
 
 // Workspace bytes of the complex path (both solve entry points).
 size_t c128_workspace_bytes(int n);

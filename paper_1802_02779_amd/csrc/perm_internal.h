@@ -32,6 +32,11 @@ constexpr int kMaxGroups = 32;   // k' groups in one layer launch
 constexpr int kBatchBlockComplex = 512;  // threads of a complex batched workgroup
 constexpr int kBatchBlockInt = 256;      // threads of an integer batched workgroup
 
+// Cache-aware tile order (perm_order.cpp): built for high parts of at most
+// this many columns; an empty slot of a padded group holds kNoTile.
+constexpr int kOrderNhMax = 18;
+constexpr uint32_t kNoTile = 0xffffffffu;
+
 constexpr int kBinomDim = kNMax + 1;  // C(i, j) for 0 <= i, j <= kNMax (all below 2^32)
 
 struct BinomTable {
@@ -104,12 +109,19 @@ struct LayerArgs {
     uint32_t t_out_start[kMaxGroups + 1];  // prefix sums of the thin groups' outputs
     uint32_t t_low_off[kMaxGroups];
     uint32_t t_high_off[kMaxGroups];
+    // Cache-aware tile order (null: colex order with XCD chunking).  Tile
+    // b - start[g] of group g is zorder[zoff[g] + b - start[g]]: its high
+    // part, or kNoTile for a padding slot.  Group starts are multiples of 8.
+    const uint32_t *zorder;
+    uint32_t zoff[kMaxGroups];
 };
 
 // Fills LayerArgs for layer k of order n with low window t; groups with
-// fewer than thin_below outputs per tile go to the per-thread path.
+// fewer than thin_below outputs per tile go to the per-thread path.  With
+// pad8 every tiled group takes a multiple of 8 workgroups (for zorder).
 // Returns the grid size (tiled workgroups + per-thread workgroups).
-uint32_t plan_layer(int n, int k, int t, int chunk, int nt_store, uint32_t thin_below, LayerArgs *a);
+uint32_t plan_layer(int n, int k, int t, int chunk, int nt_store, uint32_t thin_below, LayerArgs *a,
+                    bool pad8 = false);
 
 // Dynamic LDS bytes of a layer launch.
 size_t layer_lds_bytes_c128(const LayerArgs &a);

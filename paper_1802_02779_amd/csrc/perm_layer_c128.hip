@@ -136,6 +136,7 @@ __global__ __launch_bounds__(kLayerBlock) void k_layer_c128(const double2 *__res
     }
     const int tid = threadIdx.x;
     const TileInfo ti = decode_tile(args);
+    if (ti.empty) return;  // uniform: the whole workgroup has no tile
     const int t = args.t;
     const double2 *arow = A + (size_t)(args.k - 1) * args.n;
 

@@ -147,6 +147,7 @@ __global__ __launch_bounds__(kLayerBlock) void k_layer_modp(const uint64_t *__re
     }
     const int tid = threadIdx.x;
     const TileInfo ti = decode_tile(args);
+    if (ti.empty) return;  // uniform: the whole workgroup has no tile
     const int t = args.t, n = args.n;
     const uint32_t W = args.lds_window;
 

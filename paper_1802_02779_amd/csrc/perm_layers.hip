@@ -89,7 +89,7 @@ hipError_t ensure_tables(int device, hipStream_t s) {
 }
 
 // -------------------------------------------------------------- planning
-uint32_t plan_layer(int n, int k, int t, int chunk, int nt_store, uint32_t thin_below, LayerArgs *a) {
+uint32_t plan_layer(int n, int k, int t, int chunk, int nt_store, uint32_t thin_below, LayerArgs *a, bool pad8) {
     const int nh = n - t;
     a->n = n;
     a->k = k;
@@ -100,6 +100,7 @@ uint32_t plan_layer(int n, int k, int t, int chunk, int nt_store, uint32_t thin_
     a->ngroups = 0;
     a->thin_groups = 0;
     a->lds_window = 0;
+    a->zorder = nullptr;
     uint32_t tiles = 0, thin_out = 0;
     const int kp_lo = k - nh > 0 ? k - nh : 0;
     const int kp_hi = k < t ? k : t;
@@ -122,7 +123,7 @@ uint32_t plan_layer(int n, int k, int t, int chunk, int nt_store, uint32_t thin_
         a->ck[g] = ck;
         a->low_off[g] = lowtab_t_base(t) + lowtab_kp_off(t, kp);
         a->high_off[g] = highlist_off(m);
-        tiles += binom_host(nh, m);
+        tiles += pad8 ? (binom_host(nh, m) + 7u) & ~7u : binom_host(nh, m);
         if (kp >= 1 && binom_host(t, kp - 1) > a->lds_window) a->lds_window = binom_host(t, kp - 1);
     }
     a->start[a->ngroups] = tiles;
@@ -159,18 +160,21 @@ __device__ __forceinline__ uint32_t xcd_chunk_remap(uint32_t b, uint32_t G, uint
 struct TileInfo {
     int g, kp, m;
     uint32_t T, ck, base_out, base_low;
+    bool empty;  // padding slot of the cache-aware order: the workgroup has no tile
 };
 
 __device__ __forceinline__ TileInfo decode_tile(const LayerArgs &A) {
     TileInfo ti;
-    const uint32_t tile = xcd_chunk_remap(blockIdx.x, A.big_blocks, (uint32_t)A.chunk);
+    const uint32_t tile = A.zorder ? blockIdx.x : xcd_chunk_remap(blockIdx.x, A.big_blocks, (uint32_t)A.chunk);
     int g = 0;
     while (g + 1 < A.ngroups && A.start[g + 1] <= tile) g++;
     ti.g = g;
     ti.kp = A.kp[g];
     ti.m = A.k - ti.kp;
     ti.ck = A.ck[g];
-    ti.T = g_highlist[A.high_off[g] + (tile - A.start[g])];
+    ti.T = A.zorder ? A.zorder[A.zoff[g] + (tile - A.start[g])] : g_highlist[A.high_off[g] + (tile - A.start[g])];
+    ti.empty = ti.T == kNoTile;
+    if (ti.empty) ti.T = 0;
     uint32_t bo = 0, bl = 0, b = ti.T;
     for (int i = 1; b; i++) {
         const int h = __ffs(b) - 1 + A.t;

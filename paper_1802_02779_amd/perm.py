@@ -53,6 +53,7 @@ EXPORTS = [
     "perm_profile_enable", "perm_profile_read", "perm_multi_workspace_bytes", "perm_solve_multi",
     "perm_solve_multi_async", "perm_multi_plan_info", "perm_probe_fp64", "perm_solve_async_noalloc",
     "perm_probe_int", "perm_bunched_workspace_bytes", "perm_bunched_orientation", "perm_solve_bunched",
+    "perm_layer_tile_order",
 ]
 
 
@@ -148,6 +149,8 @@ def lib() -> ctypes.CDLL:
         L.perm_solve_bunched.restype = i32
         L.perm_probe_int.argtypes = [ctypes.POINTER(ctypes.c_double), ctypes.POINTER(ctypes.c_double), vp]
         L.perm_probe_int.restype = i32
+        L.perm_layer_tile_order.argtypes = [i32, i32, i32, i32, vp, sz, ctypes.POINTER(ctypes.c_size_t)]
+        L.perm_layer_tile_order.restype = i32
         L.perm_solve_async_noalloc.argtypes = [i32, vp, i64, vp, vp]
         L.perm_solve_async_noalloc.restype = i32
         L.perm_ryser_workspace_bytes.argtypes = [i32, i32]
@@ -447,6 +450,17 @@ def perm_probe_int(stream=None):
     a, b = ctypes.c_double(), ctypes.c_double()
     _check(lib().perm_probe_int(ctypes.byref(a), ctypes.byref(b), _stream_ptr(stream)))
     return float(a.value), float(b.value)
+
+
+def perm_layer_tile_order(n: int, t: int, k: int, value_bytes: int = 16) -> np.ndarray:
+    """The cache-aware tile order of layer k (host only): high-part masks in
+    workgroup order, 0xffffffff for padding slots."""
+    ln = ctypes.c_size_t()
+    _check(lib().perm_layer_tile_order(n, t, k, value_bytes, None, 0, ctypes.byref(ln)))
+    out = np.zeros(ln.value, dtype=np.uint32)
+    _check(lib().perm_layer_tile_order(n, t, k, value_bytes, out.ctypes.data if out.size else None, out.size,
+                                       ctypes.byref(ln)))
+    return out
 
 
 def perm_batch_workspace_bytes(dtype: int, ns: np.ndarray) -> int:

@@ -38,7 +38,7 @@ def main():
                             "where name like '%k_layer_c128%' order by start"))
     if len(rows) >= n - 1:
         print(f"\nlast step, complex layer sweep, n = {n}:\n")
-        print("| layer k | us | tiles | LDS bytes | algorithmic GB/s |")
+        print("| layer k | us | workgroups | LDS bytes | algorithmic GB/s |")
         print("|---|---|---|---|---|")
         tot = 0
         for k, (d, g, wg, lds) in zip(range(2, n + 1), rows[-(n - 1):]):

@@ -118,16 +118,16 @@ def test_tuning_validation(perm):
     with pytest.raises(perm.PermError):
         perm.perm_tuning_set(t)
     t = perm.perm_tuning_t.from_buffer_copy(saved)
-    t.layer_flags[24] = 4  # only bits 0 and 1 are defined
+    t.layer_flags[24] = 8  # only bits 0, 1 and 2 are defined
     with pytest.raises(perm.PermError):
         perm.perm_tuning_set(t)
     t = perm.perm_tuning_t.from_buffer_copy(saved)
     t.layer_t[28] = 13
-    t.layer_flags[28] = 3
+    t.layer_flags[28] = 7
     t.batch_group[12] = 128
     perm.perm_tuning_set(t)
     assert perm.perm_tuning_get().layer_t[28] == 13
-    assert perm.perm_tuning_get().layer_flags[28] == 3
+    assert perm.perm_tuning_get().layer_flags[28] == 7
     perm.perm_tuning_set(saved)
 
 

@@ -378,6 +378,55 @@ def test_int_plain_layer_width_variants(P, n):
         P.perm_tuning_set(saved)
 
 
+def test_cache_aware_tile_order(P, golden):
+    """Bit 2 of layer_flags (tiles that share high windows dealt to one XCD
+    together) changes only which workgroup computes which tile: complex
+    results stay bitwise equal to the oracle's chain, integer results exact,
+    for every low-window width, XCD run length and thin-tile threshold tried
+    and at the full sizes under the shipped tuning table."""
+    import os
+    saved = P.perm_tuning_get()
+    try:
+        for n in (16, 20, 22):
+            A = inputs.complex_gaussian(n, seed=40 + n)
+            ref = c_bits(native.per_c128(A))
+            for t in sorted({max(2, n - 18), n - 12, 8, 10, 12}):
+                for remap, thin in ((0, 0), (1, -1), (64, 16), (256, 0)):
+                    tu = P.perm_tuning_t.from_buffer_copy(saved)
+                    tu.layer_t[n] = t
+                    tu.layer_xcd_remap[n] = remap
+                    tu.layer_thin[n] = thin
+                    tu.layer_flags[n] = 4
+                    P.perm_tuning_set(tu)
+                    print(f"[gpu] tile order n={n} t={t} remap={remap} thin={thin}", flush=True)
+                    assert c_bits(P.perm_solve(A)) == ref, (n, t, remap, thin)
+        A = inputs.uniform_int(22, 0, 9, seed=8)
+        want = native.per_int(A)
+        for flags in (4, 6):
+            tu = P.perm_tuning_t.from_buffer_copy(saved)
+            tu.layer_flags[22] = flags
+            P.perm_tuning_set(tu)
+            assert P.perm_solve(A) == want, flags
+        path = os.path.join(os.path.dirname(os.path.dirname(os.path.abspath(__file__))),
+                            "paper_1802_02779_amd", "tuning", "gfx950.json")
+        if P.perm_tuning_load(path) != 0:
+            pytest.skip("the shipped tuning table is for another GPU key")
+        tu = P.perm_tuning_get()
+        for n in range(23, 31):
+            tu.layer_flags[n] |= 4
+        P.perm_tuning_set(tu)
+        for key, n, seed in FULL_COMPLEX:
+            g = golden[key]
+            print(f"[gpu] tile order full size {key}", flush=True)
+            z = P.perm_solve(inputs.complex_gaussian(n, seed=seed))
+            assert c_bits(z) == (int(g["re_bits"], 16), int(g["im_bits"], 16)), key
+        for n in (25, 27, 29, 30):
+            print(f"[gpu] tile order int n={n}", flush=True)
+            assert P.perm_solve(inputs.bernoulli01(n, seed=0)) == int(golden[f"int_n{n}_bern_s0"]["value"])
+    finally:
+        P.perm_tuning_set(saved)
+
+
 def test_full_sizes_under_shipped_tuning(P, golden):
     """The timed workloads in the configuration bench.py times: the shipped
     tuning table loaded, device-resident complex solves (n = 26, 28) and the
