@@ -11,7 +11,8 @@
 //     rank_t(L) in [0, C(t, k'));
 //   * removing a low column l in L leads to layer k-1 entries with the same T
 //     and |L| = k'-1: one contiguous window of C(t, k'-1) entries, staged in
-//     LDS and gathered through a precomputed table ("lowtab");
+//     LDS; the entry of L \ {l_p} is found from L and running binomial sums
+//     (table "lowmask" below);
 //   * removing a high column h in T leads to a window of C(t, k') entries
 //     aligned 1:1 with the tile's outputs (same rank_t(L)): read straight from
 //     HBM, coalesced.
@@ -65,20 +66,20 @@ constexpr uint32_t binom_host(int i, int j) {
     return (i < 0 || j < 0 || i > kNMax || j > kNMax) ? 0u : kBinom.v[i][j];
 }
 
-// lowtab layout: for each t in 1..kTMax, for each k' in 1..t, entries
-// [p * C(t,k') + rank_t(L)] for p in [0, k'): (rank_{t}(L \ {l_p}) | l_p << 16)
-// where l_p is the p-th smallest column of L.
-constexpr uint32_t lowtab_t_base(int t) {  // sum_{s < t} s * 2^(s-1)
+// lowmask layout: for each t in 1..kTMax, for each k' in 0..t, entry
+// [rank_t(L)] = L | (sum_i C(l_i, i)) << 16 for the k'-subsets L of [0, t)
+// (l_0 < l_1 < ...): the low part of output rank_t(L) of a tile, and the sum
+// that gives the ranks of its predecessors with one table read per output:
+//   rank_t(L \ {l_p}) = sum_{i<p} C(l_i, i+1) + sum_{i>p} C(l_i, i).
+constexpr uint32_t lowmask_t_base(int t) { return (2u << (t - 1)) - 2u; }  // sum_{s < t} 2^s
+constexpr uint32_t lowmask_kp_off(int t, int kp) {  // sum_{k'' < k'} C(t, k'')
     uint32_t s = 0;
-    for (int u = 1; u < t; u++) s += (uint32_t)u << (u - 1);
+    for (int u = 0; u < kp; u++) s += binom_host(t, u);
     return s;
 }
-constexpr uint32_t lowtab_kp_off(int t, int kp) {  // sum_{k'' < k'} k'' * C(t, k'')
-    uint32_t s = 0;
-    for (int u = 1; u < kp; u++) s += (uint32_t)u * binom_host(t, u);
-    return s;
-}
-constexpr uint32_t kLowtabEntries = lowtab_t_base(kTMax + 1);
+constexpr uint32_t kLowmaskEntries = lowmask_t_base(kTMax + 1);
+// LDS binomials of the tiled path: C(c, i) at [c * kLowBinDim + i], c < t, i <= kTMax.
+constexpr int kLowBinDim = kTMax + 1;
 
 // highlist: every mask below 2^kHighBits, sorted by (popcount, value).
 // Masks of popcount m below 2^nh are the first C(nh, m) entries of block m.
@@ -98,7 +99,7 @@ struct LayerArgs {
     int32_t kp[kMaxGroups];   // k' of group g
     uint32_t start[kMaxGroups + 1];  // first tile of group g (prefix sums)
     uint32_t ck[kMaxGroups];         // C(t, k'): outputs per tile
-    uint32_t low_off[kMaxGroups];    // lowtab offset of (t, k')
+    uint32_t lmask_off[kMaxGroups];  // lowmask offset of (t, k')
     uint32_t high_off[kMaxGroups];   // highlist offset of popcount m = k - k'
     // Groups whose tiles have fewer than `thin_below` outputs are not tiled:
     // workgroups past big_blocks give one output to each thread instead.
@@ -107,7 +108,7 @@ struct LayerArgs {
     int32_t t_kp[kMaxGroups];
     uint32_t t_ck[kMaxGroups];
     uint32_t t_out_start[kMaxGroups + 1];  // prefix sums of the thin groups' outputs
-    uint32_t t_low_off[kMaxGroups];
+    uint32_t t_lmask_off[kMaxGroups];
     uint32_t t_high_off[kMaxGroups];
     // Cache-aware tile order (null: colex order with XCD chunking).  Tile
     // b - start[g] of group g is zorder[zoff[g] + b - start[g]]: its high

@@ -35,9 +35,10 @@ hipError_t launch_pack_c128(const void *a_dev, int64_t lda, int n, void *packed,
 }
 
 // Per-thread path for groups whose tiles are too small to fill a workgroup:
-// each thread computes one whole output.  Low predecessors come through the
-// rank table from the tile's window (small, cached), high predecessors from
-// the aligned windows (neighbouring threads read neighbouring entries).
+// each thread computes one whole output.  Low predecessors are read from the
+// tile's window at ranks computed from the output's low part (small, cached),
+// high predecessors from the aligned windows (neighbouring threads read
+// neighbouring entries).
 __device__ void layer_c128_thin(const double2 *__restrict__ prev, double2 *__restrict__ next,
                                 const double2 *__restrict__ A, const LayerArgs &args, double2 *smem) {
     uint32_t *s_bin = (uint32_t *)smem;                  // C(i, j) at [i * kBinomDim + j]
@@ -69,22 +70,32 @@ __device__ void layer_c128_thin(const double2 *__restrict__ prev, double2 *__res
     // terms in groups of four: the group's loads are issued before its FMAs
     // (one memory latency per group, not per term); the FMA order is the
     // chain's
+    // low columns: one table entry gives the output's low part L and
+    // sum_i C(l_i, i); the rank of L without its p-th column is
+    // sum_{i<p} C(l_i, i+1) + sum_{i>p} C(l_i, i)
     double re = 0.0, im = 0.0;
-    const uint32_t *lt = g_lowtab + args.t_low_off[g];
-    int p = 0;
-    for (; p + 4 <= kp; p += 4) {
-        uint32_t e[4];
-        double2 w[4];
+    {
+        const uint32_t e = kp > 0 ? g_lowmask[args.t_lmask_off[g] + r] : 0u;
+        uint32_t bl = e & 0xffffu;
+        const uint32_t totb = e >> 16;
+        uint32_t pa = 0, pb = 0;
+        for (int p = 0; p < kp; p += 4) {
+            int col[4];
+            double2 w[4];
 #pragma unroll
-        for (int u = 0; u < 4; u++) e[u] = lt[(uint32_t)(p + u) * ck + r];
+            for (int u = 0; u < 4; u++)
+                if (p + u < kp) {
+                    col[u] = __ffs(bl) - 1;
+                    bl &= bl - 1;
+                    const uint32_t cb = s_bin[col[u] * kBinomDim + p + u];
+                    w[u] = prev[base_low + pa + totb - pb - cb];
+                    pa += s_bin[col[u] * kBinomDim + p + u + 1];
+                    pb += cb;
+                }
 #pragma unroll
-        for (int u = 0; u < 4; u++) w[u] = prev[base_low + (e[u] & 0xffffu)];
-#pragma unroll
-        for (int u = 0; u < 4; u++) cfma(re, im, s_arow[e[u] >> 16], w[u]);
-    }
-    for (; p < kp; p++) {
-        const uint32_t e = lt[(uint32_t)p * ck + r];
-        cfma(re, im, s_arow[e >> 16], prev[base_low + (e & 0xffffu)]);
+            for (int u = 0; u < 4; u++)
+                if (p + u < kp) cfma(re, im, s_arow[col[u]], w[u]);
+        }
     }
     // high columns ascending; the window that removes the q-th one starts at
     // base_q, with base_{q+1} = base_q + C(h_q, k'+q) - C(h_{q+1}, k'+q)
@@ -144,7 +155,9 @@ __global__ __launch_bounds__(kLayerBlock) void k_layer_c128(const double2 *__res
     double2 *s_arow = smem + args.lds_window;
     double2 *s_ha = s_arow + t;
     uint32_t *s_hb = (uint32_t *)(s_ha + 32);
+    uint32_t *s_bn = s_hb + 32;  // C(c, i) at [c * kLowBinDim + i], c < t
 
+    for (int i = tid; i < t * kLowBinDim; i += kLayerBlock) s_bn[i] = dbinom(i / kLowBinDim, i % kLowBinDim);
     if (tid < ti.m) {
         int col = 0;
         s_hb[tid] = high_window_base(ti.T, t, ti.kp, tid, &col);
@@ -159,22 +172,28 @@ __global__ __launch_bounds__(kLayerBlock) void k_layer_c128(const double2 *__res
     __syncthreads();
 
     const uint32_t ck = ti.ck;
-    const uint32_t *lt = g_lowtab + args.low_off[ti.g];
+    const uint32_t *lm = g_lowmask + args.lmask_off[ti.g];
     double2 *out = next + ti.base_out;
     for (uint32_t r = tid; r < ck; r += kLayerBlock) {
         double re = 0.0, im = 0.0;
-        // low columns, ascending (all below t)
-        int p = 0;
-        for (; p + 4 <= ti.kp; p += 4) {
-            uint32_t e[4];
-#pragma unroll
-            for (int u = 0; u < 4; u++) e[u] = lt[(uint32_t)(p + u) * ck + r];
-#pragma unroll
-            for (int u = 0; u < 4; u++) cfma(re, im, s_arow[e[u] >> 16], s_win[e[u] & 0xffffu]);
-        }
-        for (; p < ti.kp; p++) {
-            const uint32_t e = lt[(uint32_t)p * ck + r];
-            cfma(re, im, s_arow[e >> 16], s_win[e & 0xffffu]);
+        // low columns, ascending (all below t).  Output r's low part L is the
+        // r-th k'-subset of [0, t) in colex order; one table entry gives L and
+        // sum_i C(l_i, i), and the window rank of L without its p-th column,
+        // sum_{i<p} C(l_i, i+1) + sum_{i>p} C(l_i, i), follows from running
+        // sums with binomials read from LDS.
+        {
+            const uint32_t e = ti.kp > 0 ? lm[r] : 0u;
+            uint32_t b = e & 0xffffu;
+            const uint32_t totb = e >> 16;
+            uint32_t pa = 0, pb = 0;  // sum_{i<p} C(l_i, i+1), sum_{i<p} C(l_i, i)
+            for (int p = 0; b; p++) {
+                const int col = __ffs(b) - 1;
+                b &= b - 1;
+                const uint32_t cb = s_bn[col * kLowBinDim + p];
+                cfma(re, im, s_arow[col], s_win[pa + totb - pb - cb]);
+                pa += s_bn[col * kLowBinDim + p + 1];
+                pb += cb;
+            }
         }
         // high columns, ascending (all >= t); windows aligned with the tile
         int q = 0;

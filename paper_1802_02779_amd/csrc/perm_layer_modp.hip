@@ -89,10 +89,19 @@ __device__ void layer_modp_thin(const uint64_t *__restrict__ prev, uint64_t *__r
     u128 acc[RP];
 #pragma unroll
     for (int r = 0; r < RP; r++) acc[r] = 0;
-    const uint32_t *lt = g_lowtab + args.t_low_off[g];
-    for (int p = 0; p < kp; p++) {
-        const uint32_t e = lt[(uint32_t)p * ck + rr];
-        const uint32_t idx = base_low + (e & 0xffffu), col = e >> 16;
+    // low columns: the output's low part L and sum_i C(l_i, i) from one
+    // table entry, predecessor ranks from running sums
+    const uint32_t e = kp > 0 ? g_lowmask[args.t_lmask_off[g] + rr] : 0u;
+    uint32_t bl = e & 0xffffu;
+    const uint32_t totb = e >> 16;
+    uint32_t pa = 0, pb = 0;
+    for (int p = 0; bl; p++) {
+        const int col = __ffs(bl) - 1;
+        bl &= bl - 1;
+        const uint32_t cb = s_bin[col * kBinomDim + p];
+        const uint32_t idx = base_low + pa + totb - pb - cb;
+        pa += s_bin[col * kBinomDim + p + 1];
+        pb += cb;
         if (BIN) {
             if (s_arow[col] != 0) {
 #pragma unroll
@@ -155,7 +164,10 @@ __global__ __launch_bounds__(kLayerBlock) void k_layer_modp(const uint64_t *__re
     uint64_t *s_arow = smem_u + (size_t)RP * W;     // RP x t
     uint64_t *s_ha = s_arow + RP * t;               // RP x 32
     uint32_t *s_hb = (uint32_t *)(s_ha + RP * 32);  // 32
+    uint32_t *s_bn = s_hb + 32;                     // C(c, i) at [c * kLowBinDim + i], c < t
     __shared__ uint32_t s_mact;
+
+    for (int i = tid; i < t * kLowBinDim; i += kLayerBlock) s_bn[i] = dbinom(i / kLowBinDim, i % kLowBinDim);
 
     // high windows whose coefficient is nonzero for some prime, compacted
     // (a zero residue contributes nothing, so dropping it is exact)
@@ -196,7 +208,7 @@ __global__ __launch_bounds__(kLayerBlock) void k_layer_modp(const uint64_t *__re
 #pragma unroll
     for (int r = 0; r < RP; r++) pr[r] = primes[r];
     const uint32_t ck = ti.ck;
-    const uint32_t *lt = g_lowtab + args.low_off[ti.g];
+    const uint32_t *lm = g_lowmask + args.lmask_off[ti.g];
     const int mact = (int)s_mact;
     for (uint32_t rr = tid; rr < ck; rr += kLayerBlock) {
         u128 acc[RP];
@@ -205,7 +217,7 @@ __global__ __launch_bounds__(kLayerBlock) void k_layer_modp(const uint64_t *__re
         // Integer sums are exact in any order, so on the add-only path with
         // one plane (the plain 64-bit layers of a 0/1 row, most of a 0/1
         // solve) the loads of the first eight active high windows (HBM) are
-        // issued before the low terms (rank table, then LDS) and arrive
+        // issued before the low terms (one table entry, then LDS) and arrive
         // while those run (n = 30 0/1: 12.39 -> 12.12 ms).  With products or
         // more planes the registers this takes cost more than the overlap
         // gains (26x26 entries 0..9: 3.27 -> 3.47 ms), so there the windows
@@ -218,15 +230,22 @@ __global__ __launch_bounds__(kLayerBlock) void k_layer_modp(const uint64_t *__re
 #pragma unroll
                 for (int r = 0; r < RP; r++) hw[u][r] = prev[(size_t)r * plane + s_hb[u] + rr];
             }
-        // low columns: rank-table entries four at a time, then the LDS terms
-        int p = 0;
-        for (; p + 4 <= ti.kp; p += 4) {
-            uint32_t e[4];
-#pragma unroll
-            for (int u = 0; u < 4; u++) e[u] = lt[(uint32_t)(p + u) * ck + rr];
-#pragma unroll
-            for (int u = 0; u < 4; u++) {
-                const uint32_t idx = e[u] & 0xffffu, col = e[u] >> 16;
+        // low columns: output rr's low part L and sum_i C(l_i, i) come from
+        // one table entry; the window rank of L without its p-th column is
+        // sum_{i<p} C(l_i, i+1) + sum_{i>p} C(l_i, i) (running sums over the
+        // columns of L, binomials from LDS)
+        {
+            const uint32_t e = ti.kp > 0 ? lm[rr] : 0u;
+            uint32_t b = e & 0xffffu;
+            const uint32_t totb = e >> 16;
+            uint32_t pa = 0, pb = 0;  // sum_{i<p} C(l_i, i+1), sum_{i<p} C(l_i, i)
+            for (int p = 0; b; p++) {
+                const int col = __ffs(b) - 1;
+                b &= b - 1;
+                const uint32_t cb = s_bn[col * kLowBinDim + p], ca = s_bn[col * kLowBinDim + p + 1];
+                const uint32_t idx = pa + totb - pb - cb;
+                pa += ca;
+                pb += cb;
                 if (BIN) {
                     if (s_arow[col] != 0) {
 #pragma unroll
@@ -236,19 +255,6 @@ __global__ __launch_bounds__(kLayerBlock) void k_layer_modp(const uint64_t *__re
 #pragma unroll
                     for (int r = 0; r < RP; r++) acc[r] += (u128)s_arow[r * t + col] * s_win[r * W + idx];
                 }
-            }
-        }
-        for (; p < ti.kp; p++) {
-            const uint32_t e = lt[(uint32_t)p * ck + rr];
-            const uint32_t idx = e & 0xffffu, col = e >> 16;
-            if (BIN) {
-                if (s_arow[col] != 0) {
-#pragma unroll
-                    for (int r = 0; r < RP; r++) acc[r] += s_win[r * W + idx];
-                }
-            } else {
-#pragma unroll
-                for (int r = 0; r < RP; r++) acc[r] += (u128)s_arow[r * t + col] * s_win[r * W + idx];
             }
         }
         // the prefetched high windows, then the rest four at a time

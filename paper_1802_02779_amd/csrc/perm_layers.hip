@@ -11,41 +11,26 @@
 namespace permgpu {
 
 __constant__ BinomTable c_binom = make_binom();
-__device__ uint32_t g_lowtab[kLowtabEntries];
+__device__ uint32_t g_lowmask[kLowmaskEntries];
 __device__ uint32_t g_highlist[1u << kHighBits];
 
 __device__ __forceinline__ uint32_t dbinom(int i, int j) { return c_binom.v[i][j]; }
 
 // ------------------------------------------------------------------ tables
-__global__ void k_build_lowtab(int t) {
-    uint32_t L = blockIdx.x * blockDim.x + threadIdx.x;
+// lowmask entries of the k'-subsets L of [0, t), one thread per L != 0.
+__global__ void k_build_lowmask(int t) {
+    const uint32_t L = blockIdx.x * blockDim.x + threadIdx.x;
     if (L >= (1u << t) || L == 0) return;
     const int kp = __popc(L);
-    // columns of L ascending and the colex rank of L
-    int cols[kTMax];
-    uint32_t rank = 0;
-    {
-        uint32_t b = L;
-        for (int i = 0; i < kp; i++) {
-            int c = __ffs(b) - 1;
-            b &= b - 1;
-            cols[i] = c;
-            rank += dbinom(c, i + 1);
-        }
+    uint32_t rank = 0, tb = 0;  // sum_i C(l_i, i + 1) (colex rank), sum_i C(l_i, i)
+    uint32_t b = L;
+    for (int i = 0; b; i++) {
+        const int c = __ffs(b) - 1;
+        b &= b - 1;
+        rank += dbinom(c, i + 1);
+        tb += dbinom(c, i);
     }
-    uint32_t off = 0;  // lowtab_t_base(t) + lowtab_kp_off(t, kp)
-    for (int u = 1; u < t; u++) off += (uint32_t)u << (u - 1);
-    for (int u = 1; u < kp; u++) off += (uint32_t)u * dbinom(t, u);
-    const uint32_t ck = dbinom(t, kp);
-    for (int p = 0; p < kp; p++) {
-        // rank of L without its p-th column: columns above p move down one place
-        uint32_t r = 0;
-        for (int i = 0; i < kp; i++) {
-            if (i < p) r += dbinom(cols[i], i + 1);
-            else if (i > p) r += dbinom(cols[i], i);
-        }
-        g_lowtab[off + (uint32_t)p * ck + rank] = r | ((uint32_t)cols[p] << 16);
-    }
+    g_lowmask[lowmask_t_base(t) + lowmask_kp_off(t, kp) + rank] = L | (tb << 16);
 }
 
 __global__ void k_build_highlist() {
@@ -70,7 +55,7 @@ hipError_t ensure_tables(int device, hipStream_t s) {
     if (g_tables_ready[device]) return hipSuccess;
     for (int t = 1; t <= kTMax; t++) {
         uint32_t threads = 1u << t;
-        hipLaunchKernelGGL(k_build_lowtab, dim3((threads + 255) / 256), dim3(256), 0, s, t);
+        hipLaunchKernelGGL(k_build_lowmask, dim3((threads + 255) / 256), dim3(256), 0, s, t);
     }
     hipLaunchKernelGGL(k_build_highlist, dim3((1u << kHighBits) / 256), dim3(256), 0, s);
     hipError_t e = hipGetLastError();
@@ -112,7 +97,7 @@ uint32_t plan_layer(int n, int k, int t, int chunk, int nt_store, uint32_t thin_
             a->t_kp[g] = kp;
             a->t_ck[g] = ck;
             a->t_out_start[g] = thin_out;
-            a->t_low_off[g] = lowtab_t_base(t) + lowtab_kp_off(t, kp);
+            a->t_lmask_off[g] = lowmask_t_base(t) + lowmask_kp_off(t, kp);
             a->t_high_off[g] = highlist_off(m);
             thin_out += binom_host(nh, m) * ck;
             continue;
@@ -121,7 +106,7 @@ uint32_t plan_layer(int n, int k, int t, int chunk, int nt_store, uint32_t thin_
         a->kp[g] = kp;
         a->start[g] = tiles;
         a->ck[g] = ck;
-        a->low_off[g] = lowtab_t_base(t) + lowtab_kp_off(t, kp);
+        a->lmask_off[g] = lowmask_t_base(t) + lowmask_kp_off(t, kp);
         a->high_off[g] = highlist_off(m);
         tiles += pad8 ? (binom_host(nh, m) + 7u) & ~7u : binom_host(nh, m);
         if (kp >= 1 && binom_host(t, kp - 1) > a->lds_window) a->lds_window = binom_host(t, kp - 1);
@@ -133,13 +118,13 @@ uint32_t plan_layer(int n, int k, int t, int chunk, int nt_store, uint32_t thin_
 }
 
 size_t layer_lds_bytes_c128(const LayerArgs &a) {
-    const size_t tiled = (size_t)(a.lds_window + a.t + 32) * 16 + 32 * 4;
+    const size_t tiled = (size_t)(a.lds_window + a.t + 32) * 16 + 32 * 4 + (size_t)kTMax * kLowBinDim * 4;
     const size_t thin = (size_t)kBinomWords * 4 + kRowSlots * 16;
     return tiled > thin ? tiled : thin;
 }
 
 size_t layer_lds_bytes_modp(const LayerArgs &a, int rp) {
-    const size_t tiled = (size_t)rp * (a.lds_window + a.t + 32) * 8 + 32 * 4;
+    const size_t tiled = (size_t)rp * (a.lds_window + a.t + 32) * 8 + 32 * 4 + (size_t)kTMax * kLowBinDim * 4;
     const size_t thin = (size_t)kBinomWords * 4 + (size_t)rp * kRowSlots * 8;
     return tiled > thin ? tiled : thin;
 }

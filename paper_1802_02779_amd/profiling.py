@@ -345,6 +345,59 @@ def batch_sq_counters(dbs, cmd: str) -> str:
     return "\n".join(lines) + "\n"
 
 
+def layer_unit_counters(dbs, cmd: str, n: int = 28, k_lo: int = 12, k_hi: int = 16) -> str:
+    """Unit counters (SQ, TA, TCP, TCC) of the middle layers k_lo..k_hi of the
+    last n = 28 step's k_layer_c128 launches, summed over those launches,
+    from one or more rocprofv3 --pmc runs, with the ratios that say which
+    unit waits on which."""
+    tot = {}
+    for db in dbs:
+        cur = sqlite3.connect(db).cursor()
+        per = {}
+        for d, k, c, v in cur.execute("select dispatch_id, kernel_name, counter_name, value "
+                                      "from counters_collection order by dispatch_id"):
+            if "k_layer_c128" in k:
+                per.setdefault(d, {})[c] = per.get(d, {}).get(c, 0) + v
+        last = sorted(per)[-(n - 1):]
+        run = {}
+        for d in last[k_lo - 2:k_hi - 1]:
+            for c, v in per[d].items():
+                run[c] = run.get(c, 0) + v
+        for c, v in run.items():
+            tot.setdefault(c, v)  # a counter taken in several runs (GRBM_GUI_ACTIVE) counts once
+    lines = [f"commands:\n\n    {cmd}\n",
+             f"k_layer_c128, layers {k_lo}..{k_hi} of the last {n}x{n} step (sums over those launches; "
+             "GRBM_GUI_ACTIVE is summed over the 8 XCDs, TA_BUSY_avr and TCC_BUSY_avr are per-instance "
+             "averages):\n", "| counter | value |", "|---|---|"]
+    for c in sorted(tot):
+        lines.append(f"| {c} | {tot[c]:.4g} |")
+
+    def ratio(a, b, scale=1.0):
+        return tot[a] / (tot[b] * scale) if a in tot and b in tot and tot[b] else None
+    xcd_cycles = tot.get("GRBM_GUI_ACTIVE", 0) / 8.0
+    derived = [
+        ("SQ_WAIT_ANY / SQ_WAVE_CYCLES (waves waiting on a counter)", ratio("SQ_WAIT_ANY", "SQ_WAVE_CYCLES")),
+        ("SQ_WAIT_INST_ANY / SQ_WAVE_CYCLES", ratio("SQ_WAIT_INST_ANY", "SQ_WAVE_CYCLES")),
+        ("SQ_ACTIVE_INST_VALU / SQ_WAVE_CYCLES", ratio("SQ_ACTIVE_INST_VALU", "SQ_WAVE_CYCLES")),
+        ("SQ_ACTIVE_INST_LDS / SQ_WAVE_CYCLES", ratio("SQ_ACTIVE_INST_LDS", "SQ_WAVE_CYCLES")),
+        ("TA busy (TA_BUSY_avr / GPU cycles per XCD)",
+         tot["TA_BUSY_avr"] / xcd_cycles if "TA_BUSY_avr" in tot and xcd_cycles else None),
+        ("TCP stalled on data pending from L2 (TCP_PENDING_STALL_CYCLES_sum / 256 CUs / GPU cycles)",
+         tot["TCP_PENDING_STALL_CYCLES_sum"] / 256 / xcd_cycles
+         if "TCP_PENDING_STALL_CYCLES_sum" in tot and xcd_cycles else None),
+        ("L1 -> L2 read latency, cycles (TCP_TCC_READ_REQ_LATENCY_sum / TCP_TCC_READ_REQ_sum)",
+         ratio("TCP_TCC_READ_REQ_LATENCY_sum", "TCP_TCC_READ_REQ_sum")),
+        ("L2 -> memory read latency, cycles (TCC_EA0_RDREQ_LEVEL_sum / TCC_EA0_RDREQ_sum)",
+         ratio("TCC_EA0_RDREQ_LEVEL_sum", "TCC_EA0_RDREQ_sum")),
+        ("TCC busy (TCC_BUSY_avr / GPU cycles per XCD)",
+         tot["TCC_BUSY_avr"] / xcd_cycles if "TCC_BUSY_avr" in tot and xcd_cycles else None)]
+    lines.append("\n| ratio | value |\n|---|---|")
+    for name, v in derived:
+        if v is not None:
+            lines.append(f"| {name} | {v:.3f} |")
+    return "\n".join(lines) + "\n"
+
+
 if __name__ == "__main__" and len(sys.argv) > 1 and sys.argv[1] == "batch-sq":
     # "command" db [db ...]
     print(batch_sq_counters(sys.argv[3:], sys.argv[2]))
@@ -390,7 +443,12 @@ if __name__ == "__main__" and len(sys.argv) > 1 and sys.argv[1] == "modp-counter
         json.dump(data, f, indent=1)
 
 
+if __name__ == "__main__" and len(sys.argv) > 1 and sys.argv[1] == "layer-units":
+    # "command" db [db ...]
+    print(layer_unit_counters(sys.argv[3:], sys.argv[2]))
+
+
 if __name__ == "__main__" and not (len(sys.argv) > 1 and sys.argv[1] in ("counters", "multi-counters",
                                                                        "kernel-counters", "modp-counters",
-                                                                       "batch-sq")):
+                                                                       "batch-sq", "layer-units")):
     main()
