@@ -14,10 +14,13 @@
 // with the most unprocessed m-subsets (ties: lowest colex rank).  A family's
 // windows are the (m-1)-subsets of Z, each read by up to z - m + 1 of its
 // tiles; z is the largest for which C(z, m-1) windows stay within a fixed byte
-// budget.  Families go whole to the XCD with the fewest tiles so far; the
+// budget.  The families are then taken in the colex order of their z-sets
+// (so that the eight XCDs work on neighbouring families at any time and share
+// the 256 MB MALL) and go whole to the XCD with the fewest tiles so far; the
 // per-XCD lists are then evened out to floor or ceil of the group's tiles / 8
-// (a few tiles of the longest lists move to the shortest) and interleaved so that workgroup b, which the hardware
-// dispatches to XCD b % 8, takes the (b / 8)-th tile of that XCD's list.
+// (a few tiles of the longest lists move to the shortest) and interleaved
+// so that workgroup b, which the hardware dispatches to XCD b % 8, takes the
+// (b / 8)-th tile of that XCD's list.
 // Each k' group is padded to a multiple of 8 workgroups with empty slots.
 // Where no z fits (m = 0, or m + 2 > nh - 1) the tiles keep colex order in
 // runs of `chunk` per XCD, as the unordered sweep does.
@@ -117,7 +120,7 @@ void group_lists(int nh, int m, int z, int chunk, std::array<std::vector<uint32_
     std::priority_queue<E> pq;
     for (uint32_t r = 0; r < nz; r++) pq.push({newc[r], ~r});
     std::vector<uint8_t> done((size_t)1 << nh, 0);
-    std::array<uint32_t, 8> load{};
+    std::vector<std::pair<uint32_t, std::vector<uint32_t>>> fams;
     uint32_t left = cnt;
     int zc[32];
     while (left && !pq.empty()) {
@@ -130,9 +133,7 @@ void group_lists(int nh, int m, int z, int chunk, std::array<std::vector<uint32_
         }
         if (e.first <= 0) continue;
         const uint32_t Z = colex_unrank(r, z, nh);
-        int x = 0;
-        for (int i = 1; i < 8; i++)
-            if (load[i] < load[x]) x = i;
+        fams.push_back({r, {}});
         for (int i = 0, b = (int)Z; b; i++) {
             zc[i] = __builtin_ctz((uint32_t)b);
             b &= b - 1;
@@ -142,14 +143,22 @@ void group_lists(int nh, int m, int z, int chunk, std::array<std::vector<uint32_
             const uint32_t T = deposit(l, zc);
             if (done[T]) continue;
             done[T] = 1;
-            per[x].push_back(T);
-            load[x]++;
+            fams.back().second.push_back(T);
             left--;
             // every z-superset of T has one unprocessed subset less
             SupersetWalk w{T, nh, z, newc.data(), {}};
             w.init();
             w.walk(0, 0, 0u, z - m);
         }
+    }
+    std::stable_sort(fams.begin(), fams.end(), [](const auto &a, const auto &b) { return a.first < b.first; });
+    std::array<uint32_t, 8> load{};
+    for (size_t f = 0; f < fams.size(); f++) {
+        int x = 0;
+        for (int i = 1; i < 8; i++)
+            if (load[i] < load[x]) x = i;
+        for (uint32_t T : fams[f].second) per[x].push_back(T);
+        load[x] += fams[f].second.size();
     }
 }
 

@@ -75,15 +75,16 @@ def multi_layers(cur):
 
 def source_hash(root: str, n: int = 28) -> str:
     """Hash of what decides the complex layer sweep's memory traffic at order
-    n: its kernel sources and the order-n entries of the shipped tuning file.
-    Counter data is valid only while this hash is unchanged (declarations in
-    shared headers are not part of it)."""
+    n: its kernel sources, the host code that builds the cache-aware tile
+    order, and the order-n entries of the shipped tuning file.  Counter data
+    is valid only while this hash is unchanged (declarations in shared
+    headers are not part of it)."""
     import hashlib
     import json
     import os
     h = hashlib.sha256()
     csrc = os.path.join(root, "paper_1802_02779_amd", "csrc")
-    for f in ("perm_layers.hip", "perm_layer_c128.hip"):
+    for f in ("perm_layers.hip", "perm_layer_c128.hip", "perm_order.cpp"):
         with open(os.path.join(csrc, f), "rb") as fh:
             h.update(fh.read())
     tfile = os.path.join(root, "paper_1802_02779_amd", "tuning", "gfx950.json")
@@ -97,13 +98,14 @@ def source_hash(root: str, n: int = 28) -> str:
 
 def int_source_hash(root: str, n: int = 30) -> str:
     """Hash of what decides the integer sweep's memory traffic at order n:
-    its kernel sources and the order-n row of the shipped tuning file."""
+    its kernel sources, the host code that builds the cache-aware tile order,
+    and the order-n row of the shipped tuning file."""
     import hashlib
     import json
     import os
     h = hashlib.sha256()
     csrc = os.path.join(root, "paper_1802_02779_amd", "csrc")
-    for f in ("perm_layers.hip", "perm_layer_modp.hip"):
+    for f in ("perm_layers.hip", "perm_layer_modp.hip", "perm_order.cpp"):
         with open(os.path.join(csrc, f), "rb") as fh:
             h.update(fh.read())
     tfile = os.path.join(root, "paper_1802_02779_amd", "tuning", "gfx950.json")
