@@ -34,6 +34,9 @@ hipError_t launch_pack_c128(const void *a_dev, int64_t lda, int n, void *packed,
     return hipGetLastError();
 }
 
+// Terms whose loads one thread of the per-thread path has in flight together.
+constexpr int kThinGroup = 4;
+
 // Per-thread path for groups whose tiles are too small to fill a workgroup:
 // each thread computes one whole output.  Low predecessors are read from the
 // tile's window at ranks computed from the output's low part (small, cached),
@@ -44,7 +47,7 @@ __device__ void layer_c128_thin(const double2 *__restrict__ prev, double2 *__res
     uint32_t *s_bin = (uint32_t *)smem;                  // C(i, j) at [i * kBinomDim + j]
     double2 *s_arow = (double2 *)(s_bin + kBinomWords);  // row k-1 of A
     const int tid = threadIdx.x;
-    for (int i = tid; i < kBinomDim * kBinomDim; i += kLayerBlock) s_bin[i] = c_binom.v[i / kBinomDim][i % kBinomDim];
+    stage_binomials(s_bin, tid);
     if (tid < args.n) s_arow[tid] = A[(size_t)(args.k - 1) * args.n + tid];
     __syncthreads();
     const uint32_t gid = (blockIdx.x - args.big_blocks) * kLayerBlock + tid;
@@ -67,9 +70,9 @@ __device__ void layer_c128_thin(const double2 *__restrict__ prev, double2 *__res
             if (i >= 2) base_h += s_bin[h * kBinomDim + kp + i - 1];
         }
     }
-    // terms in groups of four: the group's loads are issued before its FMAs
-    // (one memory latency per group, not per term); the FMA order is the
-    // chain's
+    // terms in groups of kThinGroup: the group's loads are issued before
+    // its FMAs (one memory latency per group, not per term); the FMA order
+    // is the chain's
     // low columns: one table entry gives the output's low part L and
     // sum_i C(l_i, i); the rank of L without its p-th column is
     // sum_{i<p} C(l_i, i+1) + sum_{i>p} C(l_i, i)
@@ -79,11 +82,11 @@ __device__ void layer_c128_thin(const double2 *__restrict__ prev, double2 *__res
         uint32_t bl = e & 0xffffu;
         const uint32_t totb = e >> 16;
         uint32_t pa = 0, pb = 0;
-        for (int p = 0; p < kp; p += 4) {
-            int col[4];
-            double2 w[4];
+        for (int p = 0; p < kp; p += kThinGroup) {
+            int col[kThinGroup];
+            double2 w[kThinGroup];
 #pragma unroll
-            for (int u = 0; u < 4; u++)
+            for (int u = 0; u < kThinGroup; u++)
                 if (p + u < kp) {
                     col[u] = __ffs(bl) - 1;
                     bl &= bl - 1;
@@ -93,7 +96,7 @@ __device__ void layer_c128_thin(const double2 *__restrict__ prev, double2 *__res
                     pb += cb;
                 }
 #pragma unroll
-            for (int u = 0; u < 4; u++)
+            for (int u = 0; u < kThinGroup; u++)
                 if (p + u < kp) cfma(re, im, s_arow[col[u]], w[u]);
         }
     }
@@ -102,11 +105,11 @@ __device__ void layer_c128_thin(const double2 *__restrict__ prev, double2 *__res
     uint32_t b = T;
     int q = 1, hprev = 0;
     while (b) {
-        int hh[4];
-        uint32_t bb[4];
+        int hh[kThinGroup];
+        uint32_t bb[kThinGroup];
         int cnt = 0;
 #pragma unroll
-        for (int u = 0; u < 4; u++) {
+        for (int u = 0; u < kThinGroup; u++) {
             if (b) {
                 const int h = __ffs(b) - 1 + t;
                 b &= b - 1;
@@ -119,12 +122,12 @@ __device__ void layer_c128_thin(const double2 *__restrict__ prev, double2 *__res
                 cnt++;
             }
         }
-        double2 w[4];
+        double2 w[kThinGroup];
 #pragma unroll
-        for (int u = 0; u < 4; u++)
+        for (int u = 0; u < kThinGroup; u++)
             if (u < cnt) w[u] = prev[bb[u] + r];
 #pragma unroll
-        for (int u = 0; u < 4; u++)
+        for (int u = 0; u < kThinGroup; u++)
             if (u < cnt) cfma(re, im, s_arow[hh[u]], w[u]);
     }
     double2 *out = next + base_out + r;
@@ -146,10 +149,13 @@ __global__ __launch_bounds__(kLayerBlock) void k_layer_c128(const double2 *__res
         return;
     }
     const int tid = threadIdx.x;
-    const TileInfo ti = decode_tile(args);
+    TileInfo ti = decode_tile(args);
     if (ti.empty) return;  // uniform: the whole workgroup has no tile
     const int t = args.t;
     const double2 *arow = A + (size_t)(args.k - 1) * args.n;
+    uint32_t hb;
+    int hcol;
+    tile_bases_wave(args, ti, hb, hcol);  // every wave: the tile's bases; wave 0: the window bases
 
     double2 *s_win = smem;
     double2 *s_arow = smem + args.lds_window;
@@ -158,10 +164,9 @@ __global__ __launch_bounds__(kLayerBlock) void k_layer_c128(const double2 *__res
     uint32_t *s_bn = s_hb + 32;  // C(c, i) at [c * kLowBinDim + i], c < t
 
     for (int i = tid; i < t * kLowBinDim; i += kLayerBlock) s_bn[i] = dbinom(i / kLowBinDim, i % kLowBinDim);
-    if (tid < ti.m) {
-        int col = 0;
-        s_hb[tid] = high_window_base(ti.T, t, ti.kp, tid, &col);
-        s_ha[tid] = arow[col];
+    if (tid < ti.m) {  // wave 0 (m <= 22)
+        s_hb[tid] = hb;
+        s_ha[tid] = arow[hcol];
     }
     if (tid < t) s_arow[tid] = arow[tid];
     if (ti.kp >= 1) {

@@ -61,7 +61,7 @@ __device__ void layer_modp_thin(const uint64_t *__restrict__ prev, uint64_t *__r
     uint32_t *s_bin = (uint32_t *)smem;                 // C(i, j) at [i * kBinomDim + j]
     uint64_t *s_arow = (uint64_t *)(s_bin + kBinomWords);  // RP x kRowSlots residues of row k-1
     const int tid = threadIdx.x, n = args.n;
-    for (int i = tid; i < kBinomDim * kBinomDim; i += kLayerBlock) s_bin[i] = c_binom.v[i / kBinomDim][i % kBinomDim];
+    stage_binomials(s_bin, tid);
     if (tid < n) {
 #pragma unroll
         for (int r = 0; r < RP; r++) s_arow[r * kRowSlots + tid] = red[(size_t)r * n * n + (size_t)(args.k - 1) * n + tid];
@@ -155,8 +155,11 @@ __global__ __launch_bounds__(kLayerBlock) void k_layer_modp(const uint64_t *__re
         return;
     }
     const int tid = threadIdx.x;
-    const TileInfo ti = decode_tile(args);
+    TileInfo ti = decode_tile(args);
     if (ti.empty) return;  // uniform: the whole workgroup has no tile
+    uint32_t hbw;
+    int hcolw;
+    tile_bases_wave(args, ti, hbw, hcolw);  // every wave: the tile's bases; wave 0: the window bases
     const int t = args.t, n = args.n;
     const uint32_t W = args.lds_window;
 
@@ -172,9 +175,9 @@ __global__ __launch_bounds__(kLayerBlock) void k_layer_modp(const uint64_t *__re
     // high windows whose coefficient is nonzero for some prime, compacted
     // (a zero residue contributes nothing, so dropping it is exact)
     if (tid < 32) {
-        int col = 0;
         const bool in = tid < ti.m;
-        const uint32_t hb = in ? high_window_base(ti.T, t, ti.kp, tid, &col) : 0u;
+        const int col = in ? hcolw : 0;
+        const uint32_t hb = in ? hbw : 0u;
         uint64_t a[RP];
         bool nz = false;
 #pragma unroll

@@ -148,6 +148,19 @@ struct TileInfo {
     bool empty;  // padding slot of the cache-aware order: the workgroup has no tile
 };
 
+// Inclusive prefix sum over the 64 lanes of a wave (all lanes present).
+__device__ __forceinline__ uint32_t wave_incl_scan(uint32_t v) {
+    const int lane = threadIdx.x & 63;
+#pragma unroll
+    for (int d = 1; d < 64; d <<= 1) {
+        const uint32_t o = __shfl_up(v, d);
+        if (lane >= d) v += o;
+    }
+    return v;
+}
+
+// The workgroup's tile (group, k', m, high part T; the same in every lane).
+// Its ranks come from tile_bases_wave.
 __device__ __forceinline__ TileInfo decode_tile(const LayerArgs &A) {
     TileInfo ti;
     const uint32_t tile = A.zorder ? blockIdx.x : xcd_chunk_remap(blockIdx.x, A.big_blocks, (uint32_t)A.chunk);
@@ -157,19 +170,38 @@ __device__ __forceinline__ TileInfo decode_tile(const LayerArgs &A) {
     ti.kp = A.kp[g];
     ti.m = A.k - ti.kp;
     ti.ck = A.ck[g];
-    ti.T = A.zorder ? A.zorder[A.zoff[g] + (tile - A.start[g])] : g_highlist[A.high_off[g] + (tile - A.start[g])];
+    const uint32_t T =
+        A.zorder ? A.zorder[A.zoff[g] + (tile - A.start[g])] : g_highlist[A.high_off[g] + (tile - A.start[g])];
+    ti.T = __builtin_amdgcn_readfirstlane(T);
     ti.empty = ti.T == kNoTile;
     if (ti.empty) ti.T = 0;
-    uint32_t bo = 0, bl = 0, b = ti.T;
-    for (int i = 1; b; i++) {
-        const int h = __ffs(b) - 1 + A.t;
-        b &= b - 1;
-        bo += dbinom(h, ti.kp + i);
-        bl += dbinom(h, ti.kp - 1 + i);
-    }
-    ti.base_out = bo;
-    ti.base_low = bl;
+    ti.base_out = ti.base_low = 0;
     return ti;
+}
+
+// A tile's ranks from its high columns h_0 < ... < h_{m-1} (all >= t), with
+// A_i = C(h_i, k' + i + 1) and B_i = C(h_i, k' + i):
+//   first output rank            sum_i A_i,
+//   low window (layer k-1)       sum_i B_i,
+//   window without h_q           sum_{i<q} A_i + sum_{i>q} B_i.
+// One lane per high column and two prefix sums, so the wave gets them in
+// one round of table reads instead of a loop over the columns.  Every lane
+// of the calling wave must call it; lane q < m receives its window base and
+// h_q, every lane the tile's two bases.
+__device__ __forceinline__ void tile_bases_wave(const LayerArgs &A, TileInfo &ti, uint32_t &hb, int &col) {
+    const int lane = threadIdx.x & 63;
+    uint32_t b = ti.T;
+    for (int j = 0; j < lane && b; j++) b &= b - 1;  // lane-th set bit of T lowest
+    const bool act = lane < ti.m;
+    const int h = act ? __ffs(b) - 1 + A.t : 0;
+    const uint32_t a = act ? dbinom(h, ti.kp + lane + 1) : 0u;
+    const uint32_t c = act ? dbinom(h, ti.kp + lane) : 0u;
+    const uint32_t ia = wave_incl_scan(a), ic = wave_incl_scan(c);
+    const uint32_t tot_c = __builtin_amdgcn_readfirstlane(__shfl(ic, 63));
+    ti.base_out = __builtin_amdgcn_readfirstlane(__shfl(ia, 63));
+    ti.base_low = tot_c;
+    hb = (ia - a) + (tot_c - ic);
+    col = h;
 }
 
 // Base rank (in layer k-1) of the high window that removes the q-th high
@@ -188,5 +220,23 @@ __device__ __forceinline__ uint32_t high_window_base(uint32_t T, int t, int kp, 
 
 // Threads per workgroup of both layer kernels.
 constexpr int kLayerBlock = 256;
+
+// The whole binomial table into LDS (C(i, j) at [i * kBinomDim + j]) by a
+// workgroup of kLayerBlock threads: every thread's loads are issued before
+// its LDS writes, so the copy costs one memory latency.
+__device__ __forceinline__ void stage_binomials(uint32_t *s_bin, int tid) {
+    constexpr int kPer = (kBinomDim * kBinomDim + kLayerBlock - 1) / kLayerBlock;
+    uint32_t v[kPer];
+#pragma unroll
+    for (int u = 0; u < kPer; u++) {
+        const int i = tid + u * kLayerBlock;
+        if (i < kBinomDim * kBinomDim) v[u] = c_binom.v[i / kBinomDim][i % kBinomDim];
+    }
+#pragma unroll
+    for (int u = 0; u < kPer; u++) {
+        const int i = tid + u * kLayerBlock;
+        if (i < kBinomDim * kBinomDim) s_bin[i] = v[u];
+    }
+}
 
 }  // namespace permgpu

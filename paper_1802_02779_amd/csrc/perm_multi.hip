@@ -46,16 +46,6 @@ struct MultiTileLds {
     uint32_t base_out, kp, low_base, nh;
 };
 
-__device__ __forceinline__ uint32_t wave_incl_scan(uint32_t v) {
-    const int lane = threadIdx.x & 63;
-#pragma unroll
-    for (int d = 1; d < 64; d <<= 1) {
-        const uint32_t o = __shfl_up(v, d);
-        if (lane >= d) v += o;
-    }
-    return v;
-}
-
 // Workgroup -> tile: runs of kMultiXcdRun consecutive tiles on one XCD
 // (workgroups are dealt to the 8 XCDs in turn), so tiles that read the same
 // predecessor windows share that XCD's L2; 0 keeps the identity.  b is the
