@@ -199,10 +199,23 @@ __global__ __launch_bounds__(kLayerBlock) void k_layer_modp(const uint64_t *__re
         for (int r = 0; r < RP; r++) s_arow[r * t + tid] = red[(size_t)r * n * n + (size_t)(args.k - 1) * n + tid];
     }
     if (ti.kp >= 1) {
+        // the low window, up to four entries per plane and thread in flight
+        // before their stores
         const uint32_t w = dbinom(t, ti.kp - 1);
-        for (uint32_t i = tid; i < w; i += kLayerBlock) {
+        for (uint32_t i0 = tid; i0 < w; i0 += 4 * kLayerBlock) {
+            uint64_t v[4][RP];
 #pragma unroll
-            for (int r = 0; r < RP; r++) s_win[r * W + i] = prev[(size_t)r * plane + ti.base_low + i];
+            for (int u = 0; u < 4; u++)
+                if (i0 + u * kLayerBlock < w) {
+#pragma unroll
+                    for (int r = 0; r < RP; r++) v[u][r] = prev[(size_t)r * plane + ti.base_low + i0 + u * kLayerBlock];
+                }
+#pragma unroll
+            for (int u = 0; u < 4; u++)
+                if (i0 + u * kLayerBlock < w) {
+#pragma unroll
+                    for (int r = 0; r < RP; r++) s_win[r * W + i0 + u * kLayerBlock] = v[u][r];
+                }
         }
     }
     __syncthreads();

@@ -179,13 +179,27 @@ __device__ __forceinline__ TileInfo decode_tile(const LayerArgs &A) {
     return ti;
 }
 
+// Inclusive prefix sum over lanes 0..31 of a wave with DPP lane moves (no
+// LDS round trips): four shifts inside each row of 16 lanes, then lane 15
+// added to the next row.  Lanes 32..63 hold the scan of their own half.
+static_assert(kHighBits < 32, "tile_bases_wave keeps the high columns in lanes 0..31");
+__device__ __forceinline__ uint32_t scan32_dpp(uint32_t v) {
+    v += (uint32_t)__builtin_amdgcn_update_dpp(0, (int)v, 0x111, 0xf, 0xf, true);  // row_shr:1
+    v += (uint32_t)__builtin_amdgcn_update_dpp(0, (int)v, 0x112, 0xf, 0xf, true);  // row_shr:2
+    v += (uint32_t)__builtin_amdgcn_update_dpp(0, (int)v, 0x114, 0xf, 0xf, true);  // row_shr:4
+    v += (uint32_t)__builtin_amdgcn_update_dpp(0, (int)v, 0x118, 0xf, 0xf, true);  // row_shr:8
+    v += (uint32_t)__builtin_amdgcn_update_dpp(0, (int)v, 0x142, 0xa, 0xf, false);  // row_bcast:15
+    return v;
+}
+
 // A tile's ranks from its high columns h_0 < ... < h_{m-1} (all >= t), with
 // A_i = C(h_i, k' + i + 1) and B_i = C(h_i, k' + i):
 //   first output rank            sum_i A_i,
 //   low window (layer k-1)       sum_i B_i,
 //   window without h_q           sum_{i<q} A_i + sum_{i>q} B_i.
-// One lane per high column and two prefix sums, so the wave gets them in
-// one round of table reads instead of a loop over the columns.  Every lane
+// One lane per high column and two prefix sums over lanes 0..31, so the
+// wave gets them in one round of table reads instead of a loop over the
+// columns.  Every lane
 // of the calling wave must call it; lane q < m receives its window base and
 // h_q, every lane the tile's two bases.
 __device__ __forceinline__ void tile_bases_wave(const LayerArgs &A, TileInfo &ti, uint32_t &hb, int &col) {
@@ -196,9 +210,10 @@ __device__ __forceinline__ void tile_bases_wave(const LayerArgs &A, TileInfo &ti
     const int h = act ? __ffs(b) - 1 + A.t : 0;
     const uint32_t a = act ? dbinom(h, ti.kp + lane + 1) : 0u;
     const uint32_t c = act ? dbinom(h, ti.kp + lane) : 0u;
-    const uint32_t ia = wave_incl_scan(a), ic = wave_incl_scan(c);
-    const uint32_t tot_c = __builtin_amdgcn_readfirstlane(__shfl(ic, 63));
-    ti.base_out = __builtin_amdgcn_readfirstlane(__shfl(ia, 63));
+    // m <= kHighBits < 32: lane 31 holds the totals
+    const uint32_t ia = scan32_dpp(a), ic = scan32_dpp(c);
+    const uint32_t tot_c = __builtin_amdgcn_readlane(ic, 31);
+    ti.base_out = __builtin_amdgcn_readlane(ia, 31);
     ti.base_low = tot_c;
     hb = (ia - a) + (tot_c - ic);
     col = h;
