@@ -172,7 +172,16 @@ __global__ __launch_bounds__(kLayerBlock) void k_layer_c128(const double2 *__res
     if (ti.kp >= 1) {
         const uint32_t w = dbinom(t, ti.kp - 1);
         const double2 *src = prev + ti.base_low;
-        for (uint32_t i = tid; i < w; i += kLayerBlock) s_win[i] = src[i];
+        // two of a thread's loads in flight before their stores (one round
+        // trip less for windows above 256 entries; four in flight was slower)
+        for (uint32_t i0 = tid; i0 < w; i0 += 2 * kLayerBlock) {
+            double2 v0, v1;
+            const bool b1 = i0 + kLayerBlock < w;
+            v0 = src[i0];
+            if (b1) v1 = src[i0 + kLayerBlock];
+            s_win[i0] = v0;
+            if (b1) s_win[i0 + kLayerBlock] = v1;
+        }
     }
     __syncthreads();
 
