@@ -11,7 +11,7 @@ namespace permgpu {
 constexpr int kMultiBlock = 256;     // threads per tile workgroup
 constexpr int kMultiMMax = 64;       // distinct columns
 constexpr int kMultiWinMax = 3072;   // largest low window staged in LDS (entries)
-constexpr int kMultiThin = 64;       // tiles with at most this many outputs take one wave each
+constexpr int kMultiThin = 128;      // tiles with at most this many outputs take one wave each
 
 // Layer k of the sweep over count vectors c with |c| = k, in colex order
 // (last column most significant).  Columns 0..L-1 are "low", L..m-1 "high".

@@ -60,9 +60,17 @@ __device__ __forceinline__ uint32_t multi_tile_index(uint32_t b, uint32_t ntiles
     return (b - r) + (r % 8u) * kMultiXcdRun + r / 8u;
 }
 
+// Inclusive prefix sum over the 64 lanes of a wave: the 32-lane scan, then
+// lane 31's total added to the upper half.
+__device__ __forceinline__ uint32_t scan64_dpp(uint32_t v) {
+    v = scan32_dpp(v);
+    v += (uint32_t)__builtin_amdgcn_update_dpp(0, (int)v, 0x143, 0xc, 0xf, false);  // row_bcast:31
+    return v;
+}
+
 // Decodes tile `tile` of layer k and its predecessor tiles into t, in one
 // wave (lane = 0..63, all lanes present) with one lane per high column j
-// (prefix sums by shuffles):
+// (prefix sums by DPP lane moves):
 //   P_j  = kp + h_L + ... + h_j,
 //   base = sum_j G_j(P_j, h_j)                       (this tile, layer k),
 //   low  = sum_j G_j(P_j - 1, h_j)                   (tile h, layer k-1, low sum kp-1),
@@ -74,15 +82,15 @@ __device__ __forceinline__ void decode_tile(const MultiLayerArgs &g, uint32_t ti
     const bool act = lane < mh;
     const uint32_t x = g.hlist[g.tile0 + tile];
     const uint32_t h = act ? (x / g.hstride[lane]) % g.hradix[lane] : 0u;
-    const uint32_t ph = wave_incl_scan(h);
-    const int kp = g.k - (int)__shfl(ph, 63);
+    const uint32_t ph = scan64_dpp(h);
+    const int kp = g.k - (int)__builtin_amdgcn_readlane(ph, 63);
     const int P = kp + (int)ph;
     const uint32_t *Gj = g.G + (size_t)(act ? lane : 0) * (g.n + 1) * g.tmax1;
     const uint32_t a = act ? Gj[(size_t)P * g.tmax1 + h] : 0u;
     const uint32_t b = (act && P >= 1) ? Gj[(size_t)(P - 1) * g.tmax1 + h] : 0u;
     const uint32_t c = (act && h > 0) ? Gj[(size_t)(P - 1) * g.tmax1 + h - 1] : 0u;
-    const uint32_t pa = wave_incl_scan(a), pb = wave_incl_scan(b);
-    const uint32_t tot_a = __shfl(pa, 63), tot_b = __shfl(pb, 63);
+    const uint32_t pa = scan64_dpp(a), pb = scan64_dpp(b);
+    const uint32_t tot_a = __builtin_amdgcn_readlane(pa, 63), tot_b = __builtin_amdgcn_readlane(pb, 63);
     const uint64_t has = __ballot(act && h > 0);
     if (act && h > 0) {
         const int slot = __popcll(has & ((1ull << lane) - 1));
@@ -142,7 +150,21 @@ __global__ __launch_bounds__(kMultiBlock) void k_multi_layer_c128(const double2 
         for (uint32_t r = lane; r < nout; r += 64) {
             double re = 0.0, im = 0.0;
             if (kp >= 1) {
-                for (int c = 0; c < g.L; c++) {
+                // four columns' index and value loads in flight at a time
+                int c = 0;
+                for (; c + 4 <= g.L; c += 4) {
+                    uint32_t q[4];
+                    double2 v[4];
+#pragma unroll
+                    for (int u = 0; u < 4; u++) q[u] = lp[(size_t)(c + u) * nout + r];
+#pragma unroll
+                    for (int u = 0; u < 4; u++)
+                        if (q[u] != 0xffffu) v[u] = low[q[u]];
+#pragma unroll
+                    for (int u = 0; u < 4; u++)
+                        if (q[u] != 0xffffu) cfma(re, im, s_row[c + u], v[u]);
+                }
+                for (; c < g.L; c++) {
                     const uint32_t q = lp[(size_t)c * nout + r];
                     if (q != 0xffffu) cfma(re, im, s_row[c], low[q]);
                 }
@@ -157,9 +179,17 @@ __global__ __launch_bounds__(kMultiBlock) void k_multi_layer_c128(const double2 
     __syncthreads();
     const uint32_t kp = t.kp, base_out = t.base_out;
     if (kp >= 1) {
+        // two of a thread's loads in flight before their stores
         const uint32_t nwin = g.WL[kp - 1];
         const double2 *src = prev + t.low_base;
-        for (uint32_t e = tid; e < nwin; e += kMultiBlock) s_win[e] = src[e];
+        for (uint32_t e = tid; e < nwin; e += 2 * kMultiBlock) {
+            const bool b1 = e + kMultiBlock < nwin;
+            const double2 v0 = src[e];
+            double2 v1;
+            if (b1) v1 = src[e + kMultiBlock];
+            s_win[e] = v0;
+            if (b1) s_win[e + kMultiBlock] = v1;
+        }
     }
     __syncthreads();
     const uint32_t nout = g.WL[kp];
@@ -167,7 +197,17 @@ __global__ __launch_bounds__(kMultiBlock) void k_multi_layer_c128(const double2 
     for (uint32_t r = tid; r < nout; r += kMultiBlock) {
         double re = 0.0, im = 0.0;
         if (kp >= 1) {
-            for (int i = 0; i < g.L; i++) {
+            // eight columns' index loads in flight at a time
+            int i = 0;
+            for (; i + 8 <= g.L; i += 8) {
+                uint32_t q[8];
+#pragma unroll
+                for (int u = 0; u < 8; u++) q[u] = lp[(size_t)(i + u) * nout + r];
+#pragma unroll
+                for (int u = 0; u < 8; u++)
+                    if (q[u] != 0xffffu) cfma(re, im, s_row[i + u], s_win[q[u]]);
+            }
+            for (; i < g.L; i++) {
                 const uint32_t q = lp[(size_t)i * nout + r];
                 if (q != 0xffffu) cfma(re, im, s_row[i], s_win[q]);
             }
@@ -229,7 +269,21 @@ __device__ __forceinline__ void multi_output_modp(const uint64_t *__restrict__ p
 #pragma unroll
     for (int r = 0; r < RP; r++) acc[r] = 0;
     if (t.kp >= 1) {
-        for (int i = 0; i < g.L; i++) {
+        // four columns' index loads in flight at a time
+        int i = 0;
+        for (; i + 4 <= g.L; i += 4) {
+            uint32_t q[4];
+#pragma unroll
+            for (int u = 0; u < 4; u++) q[u] = lp[(size_t)(i + u) * nout + rr];
+#pragma unroll
+            for (int u = 0; u < 4; u++)
+                if (q[u] != 0xffffu) {
+#pragma unroll
+                    for (int r = 0; r < RP; r++)
+                        acc[r] += (u128)s_row[r][i + u] * prev[(size_t)r * plane + t.low_base + q[u]];
+                }
+        }
+        for (; i < g.L; i++) {
             const uint32_t q = lp[(size_t)i * nout + rr];
             if (q == 0xffffu) continue;
 #pragma unroll
