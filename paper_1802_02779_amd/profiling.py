@@ -14,8 +14,9 @@ import sys
 
 def main():
     db, cmd = sys.argv[1], sys.argv[2]
-    multi = len(sys.argv) > 3 and sys.argv[3] == "multi"
-    n = int(sys.argv[3]) if len(sys.argv) > 3 and not multi else 28
+    mode = sys.argv[3] if len(sys.argv) > 3 else ""
+    multi = mode == "multi"
+    n = int(mode) if mode.isdigit() else 28
     cur = sqlite3.connect(db).cursor()
     print(f"command: `{cmd}`\n")
     print("| kernel | calls | total us | average us | % |")
@@ -34,6 +35,9 @@ def main():
     if multi:
         multi_layers(cur)
         return
+    if mode == "int":
+        int_layers(cur, 30)
+        return
     rows = list(cur.execute("select duration, grid_x, workgroup_x, lds_size from kernels "
                             "where name like '%k_layer_c128%' order by start"))
     if len(rows) >= n - 1:
@@ -46,6 +50,28 @@ def main():
             tot += d
             print(f"| {k} | {d / 1000:.1f} | {g // wg} | {lds} | {by / d:.0f} |")
         print(f"\nsum of the step's layer launches: {tot / 1e6:.3f} ms")
+
+
+def int_layers(cur, n):
+    """Per-layer durations of the last exact integer solve of order n (one
+    k_layer_modp launch per layer k = 2..n): RP residue planes of 8-byte
+    values per launch, RP = 1 for the plain 64-bit layers."""
+    rows = list(cur.execute("select name, duration, grid_x, workgroup_x from kernels "
+                            "where name like '%k_layer_modp%' order by start"))
+    if len(rows) < n - 1:
+        return
+    print(f"\nlast exact integer solve, n = {n}:\n")
+    print("| layer k | kernel | us | workgroups | algorithmic GB/s |")
+    print("|---|---|---|---|---|")
+    tot = 0
+    for k, (name, d, g, wg) in zip(range(2, n + 1), rows[-(n - 1):]):
+        m = re.search(r"k_layer_modp<(\d+), *(\w+)>", name)
+        rp = int(m.group(1)) if m else 1
+        by = 8 * rp * (math.comb(n, k - 1) + math.comb(n, k))
+        tot += d
+        label = m.group(0) if m else "k_layer_modp"
+        print(f"| {k} | {label} | {d / 1000:.1f} | {g // wg} | {by / d:.0f} |")
+    print(f"\nsum of the solve's layer launches: {tot / 1e6:.3f} ms")
 
 
 def multi_layers(cur):

@@ -187,6 +187,22 @@ def test_per_abs(oracle_lib):
     assert oracle_lib.per_c128(R).imag == 0
 
 
+@pytest.mark.parametrize("n", [5, 9, 12])
+def test_per_abs_complex_rank_one(oracle_lib, n):
+    """per(|u v^T|) = n! prod_i |u_i| prod_j |v_j| for complex u, v: entrywise
+    moduli of a complex rank-one matrix (a modulus other than the Euclidean
+    one, such as |re| + |im|, fails this)."""
+    rng = np.random.default_rng(100 + n)
+    u = rng.standard_normal(n) + 1j * rng.standard_normal(n)
+    v = rng.standard_normal(n) + 1j * rng.standard_normal(n)
+    A = np.outer(u, v)
+    want = math.factorial(n) * float(np.prod(np.abs(u))) * float(np.prod(np.abs(v)))
+    assert abs(oracle_lib.per_abs(A) - want) <= 1e-12 * want
+    # a unit phase on every entry leaves every modulus, hence per(|A|), as it was
+    P = np.exp(2j * np.pi * rng.random((n, n)))
+    assert abs(oracle_lib.per_abs(A * P) - want) <= 1e-12 * want
+
+
 def test_bad_arguments_rejected(oracle_lib):
     with pytest.raises(ValueError):
         oracle_lib.per_c128(np.zeros((31, 31), dtype=np.complex128))
