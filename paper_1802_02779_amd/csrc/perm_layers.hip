@@ -148,17 +148,6 @@ struct TileInfo {
     bool empty;  // padding slot of the cache-aware order: the workgroup has no tile
 };
 
-// Inclusive prefix sum over the 64 lanes of a wave (all lanes present).
-__device__ __forceinline__ uint32_t wave_incl_scan(uint32_t v) {
-    const int lane = threadIdx.x & 63;
-#pragma unroll
-    for (int d = 1; d < 64; d <<= 1) {
-        const uint32_t o = __shfl_up(v, d);
-        if (lane >= d) v += o;
-    }
-    return v;
-}
-
 // The workgroup's tile (group, k', m, high part T; the same in every lane).
 // Its ranks come from tile_bases_wave.
 __device__ __forceinline__ TileInfo decode_tile(const LayerArgs &A) {

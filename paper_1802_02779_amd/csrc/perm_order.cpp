@@ -295,9 +295,12 @@ int apply_tile_order(int n, int k, int t, uint32_t thin, int chunk, int value_by
             }
             if (host.empty()) host.push_back(kNoTile);
             OHIP(hipMalloc(&p.dev, host.size() * 4), "hipMalloc tile order");
-            OHIP(hipMemcpyAsync(p.dev, host.data(), host.size() * 4, hipMemcpyHostToDevice, s),
-                    "upload tile order");
-            OHIP(hipStreamSynchronize(s), "hipStreamSynchronize");
+            hipError_t e = hipMemcpyAsync(p.dev, host.data(), host.size() * 4, hipMemcpyHostToDevice, s);
+            if (e == hipSuccess) e = hipStreamSynchronize(s);
+            if (e != hipSuccess) {
+                (void)hipFree(p.dev);  // nothing launched reads it yet
+                return hip_error(e, "upload tile order");
+            }
             it = g_order_plans.emplace(key, std::move(p)).first;
         }
         plan = &it->second;
