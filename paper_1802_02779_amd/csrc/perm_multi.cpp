@@ -713,7 +713,8 @@ int multi_int(const MultiPlan &P, const int64_t *a, int64_t lda, perm_int_t *out
             e1 = profile_event();
             if (e0) (void)hipEventRecord(e0, s);
         }
-        MHIP(launch_multi_layer_modp(prev, next, plane, gred, primes, cnt, g, s), "repeated-column modp layer kernel");
+        MHIP(launch_multi_layer_modp(prev, next, plane, gred, primes, cnt, g, P.max_window, s),
+             "repeated-column modp layer kernel");
         if (prof && e0 && e1) {
             (void)hipEventRecord(e1, s);
             profile_record(5, e0, e1);

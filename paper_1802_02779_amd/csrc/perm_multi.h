@@ -12,6 +12,10 @@ constexpr int kMultiBlock = 256;     // threads per tile workgroup
 constexpr int kMultiMMax = 64;       // distinct columns
 constexpr int kMultiWinMax = 3072;   // largest low window staged in LDS (entries)
 constexpr int kMultiThin = 128;      // tiles with at most this many outputs take one wave each
+// Residue sweeps stage a workgroup tile's low window (RP planes) in LDS up to
+// this size; larger windows (above 2389 entries with three planes, which only
+// plans of billions of count vectors reach) are read from cache instead.
+constexpr size_t kMultiModpLdsMax = 56 * 1024;
 
 // Layer k of the sweep over count vectors c with |c| = k, in colex order
 // (last column most significant).  Columns 0..L-1 are "low", L..m-1 "high".
@@ -58,7 +62,8 @@ hipError_t launch_multi_init_modp(const uint64_t *red, int n, int m, int rp, uin
 hipError_t launch_int64_to_modp(const uint64_t *src, uint64_t *dst, size_t plane, size_t count,
                                 const uint64_t *primes, int rp, hipStream_t s);
 hipError_t launch_multi_layer_modp(const uint64_t *prev, uint64_t *next, size_t plane, const uint64_t *red,
-                                   const uint64_t *primes, int rp, const MultiLayerArgs &g, hipStream_t s);
+                                   const uint64_t *primes, int rp, const MultiLayerArgs &g, uint32_t max_window,
+                                   hipStream_t s);
 
 // FP64 FMA probe (perm_probe.hip): `blocks` workgroups of independent
 // chains, `iters` steps each; probe_fma_flops gives the flops of one launch.

@@ -257,14 +257,16 @@ hipError_t launch_multi_init_modp(const uint64_t *red, int n, int m, int rp, uin
 
 // Residues of a[k-1][*] for RP primes; each output sums at most m <= 64
 // products below 2^122 exactly in 128 bits, then one fold (the prime 0:
-// plain 64-bit arithmetic, see out_modp).  Predecessors are read from HBM /
-// cache directly (RP planes rarely fit one LDS window).
-template <int RP>
+// plain 64-bit arithmetic, see out_modp).  High predecessors are read from
+// HBM / cache; low ones from the tile's window staged in LDS (STAGED: RP
+// planes of nwin values in s_win) or, for thin tiles, gathered from the
+// previous layer.
+template <int RP, bool STAGED>
 __device__ __forceinline__ void multi_output_modp(const uint64_t *__restrict__ prev, uint64_t *__restrict__ next,
                                                   size_t plane, const uint64_t (*s_row)[kMultiMMax],
                                                   const uint64_t *__restrict__ primes, const MultiLayerArgs &g,
                                                   const MultiTileLds &t, const uint16_t *lp, uint32_t nout,
-                                                  uint32_t rr) {
+                                                  uint32_t rr, const uint64_t *s_win, uint32_t nwin) {
     u128 acc[RP];
 #pragma unroll
     for (int r = 0; r < RP; r++) acc[r] = 0;
@@ -280,14 +282,16 @@ __device__ __forceinline__ void multi_output_modp(const uint64_t *__restrict__ p
                 if (q[u] != 0xffffu) {
 #pragma unroll
                     for (int r = 0; r < RP; r++)
-                        acc[r] += (u128)s_row[r][i + u] * prev[(size_t)r * plane + t.low_base + q[u]];
+                        acc[r] += (u128)s_row[r][i + u] *
+                                  (STAGED ? s_win[r * nwin + q[u]] : prev[(size_t)r * plane + t.low_base + q[u]]);
                 }
         }
         for (; i < g.L; i++) {
             const uint32_t q = lp[(size_t)i * nout + rr];
             if (q == 0xffffu) continue;
 #pragma unroll
-            for (int r = 0; r < RP; r++) acc[r] += (u128)s_row[r][i] * prev[(size_t)r * plane + t.low_base + q];
+            for (int r = 0; r < RP; r++)
+                acc[r] += (u128)s_row[r][i] * (STAGED ? s_win[r * nwin + q] : prev[(size_t)r * plane + t.low_base + q]);
         }
     }
     for (uint32_t w = 0; w < t.nh; w++) {
@@ -300,13 +304,15 @@ __device__ __forceinline__ void multi_output_modp(const uint64_t *__restrict__ p
 }
 
 // The same split into thin tiles (one per wave) and workgroup tiles as the
-// complex sweep.
-template <int RP>
+// complex sweep.  STAGE: workgroup tiles stage their low window in LDS (RP
+// planes of the largest window fit the launch's LDS).
+template <int RP, bool STAGE>
 __global__ __launch_bounds__(kMultiBlock) void k_multi_layer_modp(const uint64_t *__restrict__ prev,
                                                                  uint64_t *__restrict__ next, size_t plane,
                                                                  const uint64_t *__restrict__ red,
                                                                  const uint64_t *__restrict__ primes,
                                                                  const MultiLayerArgs g) {
+    extern __shared__ uint64_t s_winu[];  // RP x the largest low window
     __shared__ uint64_t s_row[RP][kMultiMMax];
     __shared__ MultiTileLds tl[kMultiBlock / 64];
     const int tid = threadIdx.x;
@@ -326,7 +332,7 @@ __global__ __launch_bounds__(kMultiBlock) void k_multi_layer_modp(const uint64_t
         const uint32_t nout = g.WL[t.kp];
         const uint16_t *lp = g.lp16 + g.kpoff[t.kp];
         for (uint32_t rr = lane; rr < nout; rr += 64)
-            multi_output_modp<RP>(prev, next, plane, s_row, primes, g, t, lp, nout, rr);
+            multi_output_modp<RP, false>(prev, next, plane, s_row, primes, g, t, lp, nout, rr, nullptr, 0);
         return;
     }
     if (tid < 64) decode_tile(g, g.thin_lo + multi_tile_index(b - g.thin_wg, g.thin_hi - g.thin_lo), tl[0], tid);
@@ -334,32 +340,54 @@ __global__ __launch_bounds__(kMultiBlock) void k_multi_layer_modp(const uint64_t
     const MultiTileLds &t = tl[0];
     const uint32_t nout = g.WL[t.kp];
     const uint16_t *lp = g.lp16 + g.kpoff[t.kp];
+    if (!STAGE) {
+        for (uint32_t rr = tid; rr < nout; rr += kMultiBlock)
+            multi_output_modp<RP, false>(prev, next, plane, s_row, primes, g, t, lp, nout, rr, nullptr, 0);
+        return;
+    }
+    // the low window of every plane in LDS, two of a thread's loads in flight
+    // before their stores
+    const uint32_t nwin = t.kp >= 1 ? g.WL[t.kp - 1] : 0u;
+    for (uint32_t e = tid; e < RP * nwin; e += 2 * kMultiBlock) {
+        const uint32_t e1 = e + kMultiBlock;
+        const uint32_t r0 = e / nwin, r1 = e1 / nwin;
+        const uint64_t v0 = prev[(size_t)r0 * plane + t.low_base + (e - r0 * nwin)];
+        uint64_t v1 = 0;
+        if (e1 < RP * nwin) v1 = prev[(size_t)r1 * plane + t.low_base + (e1 - r1 * nwin)];
+        s_winu[e] = v0;
+        if (e1 < RP * nwin) s_winu[e1] = v1;
+    }
+    __syncthreads();
     for (uint32_t rr = tid; rr < nout; rr += kMultiBlock)
-        multi_output_modp<RP>(prev, next, plane, s_row, primes, g, t, lp, nout, rr);
+        multi_output_modp<RP, true>(prev, next, plane, s_row, primes, g, t, lp, nout, rr, s_winu, nwin);
+}
+
+template <int RP>
+static void launch_multi_modp_t(const uint64_t *prev, uint64_t *next, size_t plane, const uint64_t *red,
+                                const uint64_t *primes, const MultiLayerArgs &g, uint32_t grid, uint32_t max_window,
+                                hipStream_t s) {
+    const size_t lds = (size_t)max_window * 8 * RP;
+    if (lds <= kMultiModpLdsMax)
+        hipLaunchKernelGGL((k_multi_layer_modp<RP, true>), dim3(grid), dim3(kMultiBlock), lds, s, prev, next, plane,
+                           red, primes, g);
+    else
+        hipLaunchKernelGGL((k_multi_layer_modp<RP, false>), dim3(grid), dim3(kMultiBlock), 0, s, prev, next, plane,
+                           red, primes, g);
 }
 
 hipError_t launch_multi_layer_modp(const uint64_t *prev, uint64_t *next, size_t plane, const uint64_t *red,
-                                   const uint64_t *primes, int rp, const MultiLayerArgs &g, hipStream_t s) {
-    if (g.thin_lo > g.thin_hi || g.thin_hi > g.ntiles ||
+                                   const uint64_t *primes, int rp, const MultiLayerArgs &g, uint32_t max_window,
+                                   hipStream_t s) {
+    if (max_window > (uint32_t)kMultiWinMax || g.thin_lo > g.thin_hi || g.thin_hi > g.ntiles ||
         (uint64_t)g.thin_wg * (kMultiBlock / 64) < (uint64_t)g.thin_lo + (g.ntiles - g.thin_hi))
         return hipErrorInvalidValue;
     const uint32_t grid = g.thin_wg + (g.thin_hi - g.thin_lo);
     if (grid == 0) return hipSuccess;
     switch (rp) {
-    case 1:
-        hipLaunchKernelGGL(k_multi_layer_modp<1>, dim3(grid), dim3(kMultiBlock), 0, s, prev, next, plane, red,
-                           primes, g);
-        break;
-    case 2:
-        hipLaunchKernelGGL(k_multi_layer_modp<2>, dim3(grid), dim3(kMultiBlock), 0, s, prev, next, plane, red,
-                           primes, g);
-        break;
-    case 3:
-        hipLaunchKernelGGL(k_multi_layer_modp<3>, dim3(grid), dim3(kMultiBlock), 0, s, prev, next, plane, red,
-                           primes, g);
-        break;
-    default:
-        return hipErrorInvalidValue;
+    case 1: launch_multi_modp_t<1>(prev, next, plane, red, primes, g, grid, max_window, s); break;
+    case 2: launch_multi_modp_t<2>(prev, next, plane, red, primes, g, grid, max_window, s); break;
+    case 3: launch_multi_modp_t<3>(prev, next, plane, red, primes, g, grid, max_window, s); break;
+    default: return hipErrorInvalidValue;
     }
     return hipGetLastError();
 }
